@@ -1,0 +1,628 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU reference ("oracle") for one time step of the
+ * coupled pseudopotential / thermal D2Q9 lattice-Boltzmann method for flow
+ * boiling of Mukherjee, Basu & Mondal (arXiv:2009.05264), Sec. 2 (Eqs. 1-19),
+ * with the boundary conditions of Sec. 2C.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or helper with
+ * the GPU path.
+ *
+ * Every sub-step is a separate full-grid pass in the order of the paper's
+ * algorithm (stream+BC, moments, EOS, force, velocities, source, collisions),
+ * written for a reader to check against the equations, not for speed.  All
+ * arithmetic is IEEE double.  OpenMP only splits the per-node loops over
+ * lattice rows; every reduction is a serial fixed-order loop.
+ *
+ * Readings of points the paper leaves silent, ambiguous or garbled are the
+ * ones listed in the project design notes (R1..R31); the ones that shape the
+ * code are repeated where they are used.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- D2Q9 lattice (Sec. 2A, Fig. 1; ordering: rest, 4 axis, 4 diagonal) -- */
+static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+/* ---- MRT basis (Lallemand & Luo): rows rho, e, eps, jx, qx, jy, qy, pxx, pxy */
+static const double MRT_M[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+enum { BCX_PERIODIC = 0, BCX_CHANNEL = 1 };
+enum { BCY_PERIODIC = 0, BCY_WALLS = 1 };
+enum { SIDE_S = 0, SIDE_N = 1 };
+
+/* Parameters.  Layout mirrored by the ctypes wrapper (oracle.py). */
+typedef struct {
+  double a, b, R, omega;     /* Peng-Robinson constants (Eq. 12)            */
+  double beta, c0, g;        /* Eq. 8-11: weighting, c0, interaction sign    */
+  double s_nu, s_e, s_eps, s_q; /* MRT relaxation rates                     */
+  double tau_g, c_v;         /* thermal relaxation time (Eq. 16), c_v (Eq. 19) */
+  double ga_x, ga_y;         /* buoyancy acceleration g_a (Eq. 14)           */
+  double fb_x, fb_y;         /* constant body-force density (tests only)     */
+  double u_in, T_in;         /* inlet velocity and temperature               */
+  double U_out;              /* convective-outlet speed                      */
+  double T_iso;              /* frozen temperature when isothermal           */
+  double rho_mid;            /* vapour threshold for the diagnostics         */
+  int32_t nx, ny;
+  int32_t bc_x, bc_y;
+  int32_t isothermal;        /* 1: temperature frozen at T_iso, g not evolved */
+  int32_t single_phase;      /* 1: Shan-Chen and adhesion forces switched off */
+} oc_params;
+
+/* Diagnostics of one state (order used by the wrapper). */
+enum {
+  D_MASS = 0, D_ENERGY, D_HEATER_Q, D_VAPOR, D_CLAMPED, D_NONFINITE,
+  D_P_IN, D_P_OUT, D_N
+};
+
+typedef struct {
+  oc_params P;
+  int N;             /* nx*ny                                   */
+  int64_t step;      /* number of completed steps               */
+  double *fs, *gs;   /* post-collision distributions [9][ny][nx] */
+  double *fold;      /* convective-outlet memory [3][ny], i = 3,6,7 */
+  double rbar[2];    /* mean density of the two previous states  */
+  double *Tw_s, *Tw_n, *rw_s, *rw_n, *psiw_s, *psiw_n;
+  int *heater;       /* bottom-wall heater flags [nx]            */
+  /* work arrays of the state being processed */
+  double *f, *g, *rho, *ux, *uy, *T, *p, *psi, *dpdT, *Fx, *Fy, *uax, *uay,
+      *phi;
+  double *fold_new;
+  double diag[D_N];
+} oc_state;
+
+/* ------------------------------------------------------------------------ */
+/* Peng-Robinson EOS (Eq. 12), pseudopotential (Eq. 11), (dp/dT)_rho (Eq. 19) */
+
+static double crit_T(const oc_params* P) {
+  /* a = 0.45724 R^2 Tc^2 / pc and b = 0.0778 R Tc / pc  =>  Tc below. */
+  return 0.0778 * P->a / (0.45724 * P->b * P->R);
+}
+
+/* Returns 1 when p - rho/3 has the wrong sign and psi is clamped to zero. */
+static int eos_eval(const oc_params* P, double rho, double T, double* p_out,
+                    double* psi_out, double* dpdT_out) {
+  const double Tc = crit_T(P);
+  const double kappa = 0.37464 + 1.54226 * P->omega - 0.26992 * P->omega * P->omega;
+  /* alpha(T) with sqrt(T/Tc) (reading R5 of the garbled sqrt(T/Tc^2)). */
+  const double s = sqrt(T / Tc);
+  const double sa = 1.0 + kappa * (1.0 - s);
+  const double alpha = sa * sa;
+  const double den = 1.0 + 2.0 * P->b * rho - P->b * P->b * rho * rho;
+  const double p = rho * P->R * T / (1.0 - P->b * rho) - P->a * alpha * rho * rho / den;
+  /* d alpha / dT = 2 sa * (-kappa) * d s/dT,  ds/dT = 1 / (2 sqrt(T Tc)) */
+  const double dalpha = -kappa * sa / sqrt(T * Tc);
+  const double dpdT = rho * P->R / (1.0 - P->b * rho) - P->a * rho * rho / den * dalpha;
+  /* Eq. 11 with c_s^2 = 1/3. */
+  double q = 2.0 * (p - rho / 3.0) / (P->c0 * P->g);
+  int clamped = 0;
+  if (!(q >= 0.0)) {
+    q = 0.0;
+    clamped = 1;
+  }
+  if (p_out) *p_out = p;
+  if (psi_out) *psi_out = sqrt(q);
+  if (dpdT_out) *dpdT_out = dpdT;
+  return clamped;
+}
+
+/* Eq. 3 (and Eq. 18 with rho -> T). */
+static void feq(double rho, double ux, double uy, double out[9]) {
+  const double usq = ux * ux + uy * uy;
+  for (int i = 0; i < 9; ++i) {
+    const double cu = CX[i] * ux + CY[i] * uy;
+    out[i] = W[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+  }
+}
+
+/* f* = f - M^-1 S M (f - f^eq(rho,u)) + [f^eq(rho,u+du) - f^eq(rho,u)]:
+ * the relaxation of Eq. 2 generalised to MRT (S = I/tau gives Eq. 2 exactly)
+ * plus the exact-difference forcing of Eq. 5. */
+static void collide_f(const oc_params* P, const double f[9], double rho,
+                      double ux, double uy, double dux, double duy,
+                      double out[9]) {
+  double e0[9], e1[9], d[9], m[9];
+  feq(rho, ux, uy, e0);
+  feq(rho, ux + dux, uy + duy, e1);
+  for (int i = 0; i < 9; ++i) d[i] = f[i] - e0[i];
+  for (int k = 0; k < 9; ++k) {
+    m[k] = 0.0;
+    for (int i = 0; i < 9; ++i) m[k] += MRT_M[k][i] * d[i];
+  }
+  const double S[9] = {0.0, P->s_e, P->s_eps, 0.0, P->s_q, 0.0, P->s_q, P->s_nu, P->s_nu};
+  double norm[9];
+  for (int k = 0; k < 9; ++k) {
+    norm[k] = 0.0;
+    for (int i = 0; i < 9; ++i) norm[k] += MRT_M[k][i] * MRT_M[k][i];
+  }
+  for (int i = 0; i < 9; ++i) {
+    /* M^-1 = M^T diag(1/|row_k|^2) because the rows of M are orthogonal. */
+    double r = 0.0;
+    for (int k = 0; k < 9; ++k) r += MRT_M[k][i] / norm[k] * S[k] * m[k];
+    out[i] = f[i] - r + (e1[i] - e0[i]);
+  }
+}
+
+/* Eq. 16 (with the relaxation sign of reading R9), Eq. 18. */
+static void collide_g(const oc_params* P, const double g[9], double T,
+                      double uax, double uay, double phi, double out[9]) {
+  double ge[9];
+  feq(T, uax, uay, ge);
+  for (int i = 0; i < 9; ++i)
+    out[i] = g[i] - (g[i] - ge[i]) / P->tau_g + W[i] * phi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid helpers */
+
+static int wrap(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* x index of the wall-map entry of a solid cell at column xs (corner solid
+ * cells take the value of the nearest in-range cell, or wrap when periodic). */
+static int wall_x(const oc_params* P, int xs) {
+  return P->bc_x == BCX_PERIODIC ? wrap(xs, P->nx) : clampi(xs, 0, P->nx - 1);
+}
+
+static int is_solid_row(const oc_params* P, int y) {
+  return P->bc_y == BCY_WALLS && (y < 0 || y >= P->ny);
+}
+
+#define AT(arr, i, x, y) (arr)[(size_t)(i) * S->N + (size_t)(y) * P->nx + (x)]
+#define NODE(arr, x, y) (arr)[(size_t)(y) * P->nx + (x)]
+
+/* ------------------------------------------------------------------------ */
+/* Sub-step S8 (pull stream + boundary conditions): builds f, g of the new
+ * state from the post-collision arrays fs, gs.  Rules, in precedence order:
+ *  1. source in a solid wall row: halfway bounce-back for f, anti-bounce-back
+ *     g_i = -g*_opp(x) + 2 w_i T_wall for g (Sec. 2C);
+ *  2. source is a fluid node (periodic wrap where periodic): plain streaming;
+ *  3. source is the inlet ghost column x=-1: non-equilibrium bounce-back
+ *     (Zou-He) for the velocity, anti-bounce-back with the inlet state for g;
+ *  4. source is the outlet ghost column x=nx: convective outlet for f, zero
+ *     temperature gradient for g. */
+static void stream_and_bc(oc_state* S) {
+  const oc_params* P = &S->P;
+  const int nx = P->nx, ny = P->ny;
+
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      for (int i = 0; i < 9; ++i) {
+        int xs = x - CX[i], ys = y - CY[i];
+        double fv = 0.0, gv = 0.0; /* ghost sources are overwritten below */
+        if (is_solid_row(P, ys)) {
+          const int o = OPP[i];
+          const int xm = wall_x(P, xs);
+          const double Tw = ys < 0 ? S->Tw_s[xm] : S->Tw_n[xm];
+          fv = AT(S->fs, o, x, y);
+          gv = -AT(S->gs, o, x, y) + 2.0 * W[i] * Tw;
+        } else {
+          if (P->bc_y == BCY_PERIODIC) ys = wrap(ys, ny);
+          int fluid = 1;
+          if (P->bc_x == BCX_PERIODIC)
+            xs = wrap(xs, nx);
+          else if (xs < 0 || xs >= nx)
+            fluid = 0; /* inlet or outlet ghost: filled below */
+          if (fluid) {
+            fv = AT(S->fs, i, xs, ys);
+            gv = AT(S->gs, i, xs, ys);
+          }
+        }
+        AT(S->f, i, x, y) = fv;
+        AT(S->g, i, x, y) = gv;
+      }
+    }
+  }
+
+  if (P->bc_x != BCX_CHANNEL) return;
+
+  /* Rule 3: inlet at x = 0.  Unknowns are the directions 1, 5, 8 still
+   * unset after rules 1-2 (the wall rule wins at the corners). */
+  for (int y = 0; y < ny; ++y) {
+    double f[9];
+    for (int i = 0; i < 9; ++i) f[i] = AT(S->f, i, 0, y);
+    const double u = P->u_in;
+    const double rin = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7])) / (1.0 - u);
+    /* direction i is unknown when its source is the ghost, not a wall cell */
+    const int unk1 = 1, unk5 = !is_solid_row(P, y - 1), unk8 = !is_solid_row(P, y + 1);
+    if (unk1) AT(S->f, 1, 0, y) = f[3] + 2.0 / 3.0 * rin * u;
+    if (unk5) AT(S->f, 5, 0, y) = f[7] - 0.5 * (f[2] - f[4]) + rin * u / 6.0;
+    if (unk8) AT(S->f, 8, 0, y) = f[6] + 0.5 * (f[2] - f[4]) + rin * u / 6.0;
+    for (int i = 0; i < 9; ++i) {
+      if (CX[i] != 1 || is_solid_row(P, y - CY[i])) continue;
+      /* even part of g^eq(T_in, u_in) (Eq. 18), anti-bounce-back form */
+      const double cu = CX[i] * u;
+      const double geven = W[i] * P->T_in * (1.0 + 4.5 * cu * cu - 1.5 * u * u);
+      AT(S->g, i, 0, y) = -AT(S->gs, OPP[i], 0, y) + 2.0 * geven;
+    }
+  }
+
+  /* Rule 4: convective outlet at x = nx-1, using the values at x = nx-2
+   * that rules 1-2 have just produced. */
+  const int ko[3] = {3, 6, 7};
+  for (int y = 0; y < ny; ++y) {
+    for (int k = 0; k < 3; ++k) {
+      const int i = ko[k];
+      if (!is_solid_row(P, y - CY[i])) {
+        AT(S->f, i, nx - 1, y) =
+            (S->fold[k * ny + y] + P->U_out * AT(S->f, i, nx - 2, y)) / (1.0 + P->U_out);
+        AT(S->g, i, nx - 1, y) = AT(S->g, i, nx - 2, y);
+      }
+      S->fold_new[k * ny + y] = AT(S->f, i, nx - 1, y);
+    }
+  }
+}
+
+/* Sub-steps S1-S5 on the state produced by stream_and_bc(). */
+static void macro_and_forces(oc_state* S) {
+  const oc_params* P = &S->P;
+  const int nx = P->nx, ny = P->ny;
+  int nclamp = 0;
+
+  /* S1 moments (Eqs. 4, 6 with /rho (R1), 17) and S2 EOS. */
+#pragma omp parallel for schedule(static) reduction(+ : nclamp)
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      double rho = 0.0, jx = 0.0, jy = 0.0, T = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        const double fi = AT(S->f, i, x, y);
+        rho += fi;
+        jx += CX[i] * fi;
+        jy += CY[i] * fi;
+      }
+      if (P->isothermal) {
+        T = P->T_iso;
+      } else {
+        for (int i = 0; i < 9; ++i) T += AT(S->g, i, x, y);
+      }
+      NODE(S->rho, x, y) = rho;
+      NODE(S->ux, x, y) = jx / rho;
+      NODE(S->uy, x, y) = jy / rho;
+      NODE(S->T, x, y) = T;
+      nclamp += eos_eval(P, rho, T, &NODE(S->p, x, y), &NODE(S->psi, x, y),
+                         &NODE(S->dpdT, x, y));
+    }
+  }
+
+  /* Diagnostics of this state (serial, fixed order). */
+  double mass = 0.0, energy = 0.0, q = 0.0, nvap = 0.0, nnf = 0.0;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const double r = NODE(S->rho, x, y), t = NODE(S->T, x, y);
+      mass += r;
+      energy += t;
+      if (r < P->rho_mid) nvap += 1.0;
+      if (!isfinite(r) || !isfinite(t)) nnf += 1.0;
+    }
+  if (P->bc_y == BCY_WALLS)
+    for (int x = 0; x < nx; ++x)
+      if (S->heater[x]) q += 2.0 * (S->Tw_s[x] - NODE(S->T, x, 0));
+  S->diag[D_MASS] = mass;
+  S->diag[D_ENERGY] = energy;
+  S->diag[D_HEATER_Q] = q;
+  S->diag[D_VAPOR] = nvap;
+  S->diag[D_CLAMPED] = (double)nclamp;
+  S->diag[D_NONFINITE] = nnf;
+  S->diag[D_P_IN] = NODE(S->p, 0, ny / 2);
+  S->diag[D_P_OUT] = NODE(S->p, nx - 1, ny / 2);
+
+  /* S3 forces.  Eq. 9 with psi(x1) inside the sums (R3) and G1 = 2g,
+   * G2 = g/2 (Eq. 10, R4).  Adhesion (Eq. 15): a solid neighbour enters the
+   * same two sums with the pseudopotential of the false wall density,
+   * psi_w = psi(rho_w, T_wall) (R8), so that rho_w equal to the local density
+   * exerts no net force.  Buoyancy Eq. 14 in the (rho - rho_avg) g_a form
+   * with rho_avg the mean density of the state two steps back (R7). */
+  const double G1 = 2.0 * P->g, G2 = 0.5 * P->g;
+  const double rbar = S->rbar[1];
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      const double psi0 = NODE(S->psi, x, y);
+      double fsc_x = 0.0, fsc_y = 0.0, fw_x = 0.0, fw_y = 0.0;
+      for (int i = 1; i < 9; ++i) {
+        const double Gi = i <= 4 ? G1 : G2;
+        int x1 = x + CX[i], y1 = y + CY[i];
+        if (is_solid_row(P, y1)) {
+          const int xm = wall_x(P, x1);
+          const double pw = y1 < 0 ? S->psiw_s[xm] : S->psiw_n[xm];
+          fw_x += -P->beta * psi0 * Gi * pw * CX[i] - 0.5 * (1.0 - P->beta) * Gi * pw * pw * CX[i];
+          fw_y += -P->beta * psi0 * Gi * pw * CY[i] - 0.5 * (1.0 - P->beta) * Gi * pw * pw * CY[i];
+        } else {
+          if (P->bc_y == BCY_PERIODIC) y1 = wrap(y1, ny);
+          x1 = P->bc_x == BCX_PERIODIC ? wrap(x1, nx) : clampi(x1, 0, nx - 1);
+          const double ps1 = NODE(S->psi, x1, y1);
+          fsc_x += -P->beta * psi0 * Gi * ps1 * CX[i] - 0.5 * (1.0 - P->beta) * Gi * ps1 * ps1 * CX[i];
+          fsc_y += -P->beta * psi0 * Gi * ps1 * CY[i] - 0.5 * (1.0 - P->beta) * Gi * ps1 * ps1 * CY[i];
+        }
+      }
+      if (P->single_phase) fsc_x = fsc_y = fw_x = fw_y = 0.0;
+      const double rho = NODE(S->rho, x, y);
+      const double Fx = fsc_x + fw_x + (rho - rbar) * P->ga_x + P->fb_x;
+      const double Fy = fsc_y + fw_y + (rho - rbar) * P->ga_y + P->fb_y;
+      NODE(S->Fx, x, y) = Fx;
+      NODE(S->Fy, x, y) = Fy;
+      /* S4: actual velocity, Eq. 7 with the tau_f factor read as 1 (R2). */
+      NODE(S->uax, x, y) = NODE(S->ux, x, y) + Fx / (2.0 * rho);
+      NODE(S->uay, x, y) = NODE(S->uy, x, y) + Fy / (2.0 * rho);
+    }
+  }
+
+  /* S5: phase-change source, second form of Eq. 19 (R10), u = u_act, with a
+   * second-order central difference for div u (R11).  Ghost values at the
+   * domain edge:  inlet/outlet ghost columns copy the boundary column.  At a
+   * halfway bounce-back wall the two parts of phi = T div u - T (dp/dT)/(rho
+   * c_v) div u use the closure consistent with the discrete transport they
+   * stand for (R11'): the T div u part cancels the conservative advection of
+   * the g equation, whose anti-bounce-back wall returns populations with the
+   * adjacent velocity, so its ghost copies u_y of the wall-adjacent node; the
+   * compression part follows the mass flux, which bounce-back makes zero at
+   * the wall, so its ghost is the mirror -u_y. */
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      int xe = x + 1, xw = x - 1;
+      if (P->bc_x == BCX_PERIODIC) {
+        xe = wrap(xe, nx);
+        xw = wrap(xw, nx);
+      } else {
+        xe = clampi(xe, 0, nx - 1);
+        xw = clampi(xw, 0, nx - 1);
+      }
+      const double dux = 0.5 * (NODE(S->uax, xe, y) - NODE(S->uax, xw, y));
+      const double uy0 = NODE(S->uay, x, y);
+      double uyn_c, uys_c, uyn_m, uys_m;
+      if (is_solid_row(P, y + 1)) {
+        uyn_c = uy0;
+        uyn_m = -uy0;
+      } else {
+        uyn_c = uyn_m = NODE(S->uay, x, P->bc_y == BCY_PERIODIC ? wrap(y + 1, ny) : y + 1);
+      }
+      if (is_solid_row(P, y - 1)) {
+        uys_c = uy0;
+        uys_m = -uy0;
+      } else {
+        uys_c = uys_m = NODE(S->uay, x, P->bc_y == BCY_PERIODIC ? wrap(y - 1, ny) : y - 1);
+      }
+      const double div_adv = dux + 0.5 * (uyn_c - uys_c);
+      const double div_mass = dux + 0.5 * (uyn_m - uys_m);
+      const double rho = NODE(S->rho, x, y);
+      const double T = NODE(S->T, x, y);
+      NODE(S->phi, x, y) = T * div_adv - T * NODE(S->dpdT, x, y) / (rho * P->c_v) * div_mass;
+    }
+  }
+}
+
+/* Full state evaluation: stream+BC then S1-S5.  Leaves fs/gs untouched. */
+static void evaluate(oc_state* S) {
+  stream_and_bc(S);
+  macro_and_forces(S);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public API (called through ctypes by the tests and the CPU baseline). */
+
+void* oc_create(const oc_params* P) {
+  if (P->nx < 3 || P->ny < 3) return NULL;
+  oc_state* S = (oc_state*)calloc(1, sizeof(oc_state));
+  S->P = *P;
+  S->N = P->nx * P->ny;
+  const size_t N = (size_t)S->N;
+  S->fs = calloc(9 * N, sizeof(double));
+  S->gs = calloc(9 * N, sizeof(double));
+  S->f = calloc(9 * N, sizeof(double));
+  S->g = calloc(9 * N, sizeof(double));
+  double** arrs[] = {&S->rho, &S->ux, &S->uy, &S->T, &S->p, &S->psi, &S->dpdT,
+                     &S->Fx, &S->Fy, &S->uax, &S->uay, &S->phi};
+  for (size_t k = 0; k < sizeof(arrs) / sizeof(arrs[0]); ++k) *arrs[k] = calloc(N, sizeof(double));
+  S->fold = calloc(3 * (size_t)P->ny, sizeof(double));
+  S->fold_new = calloc(3 * (size_t)P->ny, sizeof(double));
+  double** maps[] = {&S->Tw_s, &S->Tw_n, &S->rw_s, &S->rw_n, &S->psiw_s, &S->psiw_n};
+  for (size_t k = 0; k < 6; ++k) *maps[k] = calloc((size_t)P->nx, sizeof(double));
+  S->heater = calloc((size_t)P->nx, sizeof(int));
+  /* default walls: inlet temperature, wall density equal to nothing (psi 0) */
+  for (int x = 0; x < P->nx; ++x) {
+    S->Tw_s[x] = S->Tw_n[x] = P->T_in;
+  }
+  return S;
+}
+
+void oc_destroy(void* h) {
+  oc_state* S = (oc_state*)h;
+  if (!S) return;
+  double* arrs[] = {S->fs, S->gs, S->f, S->g, S->rho, S->ux, S->uy, S->T, S->p,
+                    S->psi, S->dpdT, S->Fx, S->Fy, S->uax, S->uay, S->phi,
+                    S->fold, S->fold_new, S->Tw_s, S->Tw_n, S->rw_s, S->rw_n,
+                    S->psiw_s, S->psiw_n};
+  for (size_t k = 0; k < sizeof(arrs) / sizeof(arrs[0]); ++k) free(arrs[k]);
+  free(S->heater);
+  free(S);
+}
+
+/* Wall maps of one side (0 = south/bottom, 1 = north/top): wall temperature,
+ * false wall density rho_w (Eq. 15) and heater flags (bottom only). */
+void oc_set_wall(void* h, int side, const double* Tw, const double* rho_w, const int* heater) {
+  oc_state* S = (oc_state*)h;
+  const oc_params* P = &S->P;
+  double* T = side == SIDE_S ? S->Tw_s : S->Tw_n;
+  double* r = side == SIDE_S ? S->rw_s : S->rw_n;
+  double* ps = side == SIDE_S ? S->psiw_s : S->psiw_n;
+  for (int x = 0; x < P->nx; ++x) {
+    T[x] = Tw[x];
+    r[x] = rho_w[x];
+    eos_eval(P, r[x], T[x], NULL, &ps[x], NULL);
+    if (side == SIDE_S) S->heater[x] = heater ? heater[x] : 0;
+  }
+}
+
+/* Counter-based generator used for the seeded initial noise: SplitMix64
+ * (Steele, Lea & Flood 2014), output function applied to state = z. */
+uint64_t oc_splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* Uniform variate in [-1, 1) of node (x, y) for a seed. */
+double oc_noise(uint64_t seed, int nx, int x, int y) {
+  const uint64_t k = seed ^ (uint64_t)((int64_t)y * nx + x);
+  const double u = (double)(oc_splitmix64(k) >> 11) * (1.0 / 9007199254740992.0);
+  return 2.0 * u - 1.0;
+}
+
+/* Initial state: post-collision f = f^eq(rho0, 0), g = w_i T0; rho0 either
+ * the given array or rho_u (1 + noise * xi(x, y)). */
+void oc_init(void* h, const double* rho0, const double* T0, double rho_u, double T_u,
+             double noise, uint64_t seed) {
+  oc_state* S = (oc_state*)h;
+  const oc_params* P = &S->P;
+  const int nx = P->nx, ny = P->ny;
+  double sum = 0.0;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double r = rho0 ? NODE(rho0, x, y) : rho_u * (1.0 + noise * oc_noise(seed, nx, x, y));
+      const double t = T0 ? NODE(T0, x, y) : T_u;
+      for (int i = 0; i < 9; ++i) {
+        AT(S->fs, i, x, y) = W[i] * r;
+        AT(S->gs, i, x, y) = W[i] * t;
+      }
+      sum += r;
+    }
+  const int ko[3] = {3, 6, 7};
+  for (int k = 0; k < 3; ++k)
+    for (int y = 0; y < ny; ++y) S->fold[k * ny + y] = AT(S->fs, ko[k], nx - 1, y);
+  S->rbar[0] = S->rbar[1] = sum / (double)S->N;
+  S->step = 0;
+}
+
+/* Advance n time steps. */
+void oc_step(void* h, int64_t n) {
+  oc_state* S = (oc_state*)h;
+  const oc_params* P = &S->P;
+  const int nx = P->nx, ny = P->ny;
+  for (int64_t it = 0; it < n; ++it) {
+    evaluate(S);
+    /* S6, S7 collisions. */
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y) {
+      for (int x = 0; x < nx; ++x) {
+        double f[9], g[9], fo[9], go[9];
+        for (int i = 0; i < 9; ++i) {
+          f[i] = AT(S->f, i, x, y);
+          g[i] = AT(S->g, i, x, y);
+        }
+        const double rho = NODE(S->rho, x, y);
+        collide_f(P, f, rho, NODE(S->ux, x, y), NODE(S->uy, x, y),
+                  NODE(S->Fx, x, y) / rho, NODE(S->Fy, x, y) / rho, fo);
+        for (int i = 0; i < 9; ++i) AT(S->fs, i, x, y) = fo[i];
+        if (!P->isothermal) {
+          collide_g(P, g, NODE(S->T, x, y), NODE(S->uax, x, y), NODE(S->uay, x, y),
+                    NODE(S->phi, x, y), go);
+          for (int i = 0; i < 9; ++i) AT(S->gs, i, x, y) = go[i];
+        }
+      }
+    }
+    if (P->bc_x == BCX_CHANNEL) memcpy(S->fold, S->fold_new, 3 * (size_t)ny * sizeof(double));
+    S->rbar[1] = S->rbar[0];
+    S->rbar[0] = S->diag[D_MASS] / (double)S->N;
+    S->step++;
+  }
+}
+
+int64_t oc_step_count(void* h) { return ((oc_state*)h)->step; }
+
+/* Fields of the current state (post-stream): rho, u_act, T, and optionally
+ * p, psi, F, phi.  Any pointer may be NULL.  Also refreshes the diagnostics. */
+void oc_fields(void* h, double* rho, double* uax, double* uay, double* T, double* p,
+               double* psi, double* Fx, double* Fy, double* phi) {
+  oc_state* S = (oc_state*)h;
+  evaluate(S);
+  const size_t N = (size_t)S->N;
+  if (rho) memcpy(rho, S->rho, N * sizeof(double));
+  if (uax) memcpy(uax, S->uax, N * sizeof(double));
+  if (uay) memcpy(uay, S->uay, N * sizeof(double));
+  if (T) memcpy(T, S->T, N * sizeof(double));
+  if (p) memcpy(p, S->p, N * sizeof(double));
+  if (psi) memcpy(psi, S->psi, N * sizeof(double));
+  if (Fx) memcpy(Fx, S->Fx, N * sizeof(double));
+  if (Fy) memcpy(Fy, S->Fy, N * sizeof(double));
+  if (phi) memcpy(phi, S->phi, N * sizeof(double));
+}
+
+/* Diagnostics of the current state (D_N doubles). */
+void oc_diag(void* h, double* out) {
+  oc_state* S = (oc_state*)h;
+  evaluate(S);
+  memcpy(out, S->diag, sizeof(S->diag));
+}
+
+/* Post-collision arrays (the stored state), [9][ny][nx] each. */
+void oc_get_state(void* h, double* fs, double* gs) {
+  oc_state* S = (oc_state*)h;
+  memcpy(fs, S->fs, 9 * (size_t)S->N * sizeof(double));
+  memcpy(gs, S->gs, 9 * (size_t)S->N * sizeof(double));
+}
+void oc_set_state(void* h, const double* fs, const double* gs) {
+  oc_state* S = (oc_state*)h;
+  memcpy(S->fs, fs, 9 * (size_t)S->N * sizeof(double));
+  memcpy(S->gs, gs, 9 * (size_t)S->N * sizeof(double));
+}
+/* Post-stream (pre-collision) distributions of the current state. */
+void oc_get_streamed(void* h, double* f, double* g) {
+  oc_state* S = (oc_state*)h;
+  evaluate(S);
+  memcpy(f, S->f, 9 * (size_t)S->N * sizeof(double));
+  memcpy(g, S->g, 9 * (size_t)S->N * sizeof(double));
+}
+void oc_get_rbar(void* h, double* out2) {
+  oc_state* S = (oc_state*)h;
+  out2[0] = S->rbar[0];
+  out2[1] = S->rbar[1];
+}
+
+/* ---- single-node entry points for the pin tests ------------------------ */
+int oc_eos(const oc_params* P, double rho, double T, double* out3) {
+  return eos_eval(P, rho, T, &out3[0], &out3[1], &out3[2]);
+}
+double oc_Tc(const oc_params* P) { return crit_T(P); }
+void oc_feq(double rho, double ux, double uy, double* out9) { feq(rho, ux, uy, out9); }
+/* f collision at one node from its pre-collision f and the force F. */
+void oc_collide_f_node(const oc_params* P, const double* f, double Fx, double Fy, double* out) {
+  double rho = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    rho += f[i];
+    jx += CX[i] * f[i];
+    jy += CY[i] * f[i];
+  }
+  collide_f(P, f, rho, jx / rho, jy / rho, Fx / rho, Fy / rho, out);
+}
+void oc_collide_g_node(const oc_params* P, const double* g, double uax, double uay,
+                       double phi, double* out) {
+  double T = 0.0;
+  for (int i = 0; i < 9; ++i) T += g[i];
+  collide_g(P, g, T, uax, uay, phi, out);
+}
+void oc_mrt_matrix(double* M81) {
+  for (int k = 0; k < 9; ++k)
+    for (int i = 0; i < 9; ++i) M81[k * 9 + i] = MRT_M[k][i];
+}
