@@ -1,0 +1,181 @@
+/*
+ * lbmflow.h -- C ABI of the MI355X (gfx950) implementation of one coupled
+ * time step of the pseudopotential / thermal D2Q9 lattice-Boltzmann method
+ * for flow boiling (Mukherjee, Basu & Mondal, arXiv:2009.05264).
+ *
+ * The operation behind every entry point is the per-time-step update of
+ * Sec. 2 of the paper:
+ *   - pull streaming with the boundary rules of Sec. 2C: halfway bounce-back
+ *     at no-slip walls, non-equilibrium (Zou-He) bounce-back at the velocity
+ *     inlet, anti-bounce-back for temperature, a convective outlet with zero
+ *     temperature gradient;
+ *   - moments (Eqs. 4, 6, 17), the Peng-Robinson EOS (Eq. 12) and the
+ *     pseudopotential (Eq. 11);
+ *   - the beta-weighted Shan-Chen force (Eqs. 8-10), adhesion through the
+ *     false wall density (Eq. 15), buoyancy (Eq. 14);
+ *   - exact-difference forcing (Eqs. 5, 7) in a multiple-relaxation-time
+ *     collision that reduces to the BGK operator of Eq. 2 when all rates are
+ *     equal;
+ *   - the thermal distribution (Eqs. 16-18) with the phase-change source of
+ *     the second form of Eq. 19.
+ *
+ * Conventions
+ *   - Every call returns int: LBM_OK (0) or a negative LBM_E_* code; the
+ *     message of the last failure on the calling thread is lbm_last_error().
+ *     No call aborts and no C++ exception crosses the ABI.
+ *   - Handles are opaque.  One handle is used by one host thread at a time.
+ *   - Host arrays are caller-owned, row-major [ny][nx] (x fastest), copied
+ *     in or out during the call.
+ *   - Device memory is either allocated by the library (dev_mem == NULL at
+ *     lbm_create, freed by lbm_destroy) or supplied by the caller (a device
+ *     pointer of at least lbm_required_bytes() bytes, 256-byte aligned, owned
+ *     and freed by the caller after lbm_destroy).
+ *   - Streams are caller-owned hipStream_t passed as void*; NULL selects a
+ *     stream created by the library.  lbm_step and lbm_batch_step only
+ *     enqueue work; lbm_sync blocks until it is done.  Read calls
+ *     synchronise the stream themselves.
+ *   - Fields are in lattice units.  Sizes are int32 (nx, ny < 32768).
+ */
+#ifndef LBMFLOW_H
+#define LBMFLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_E_INVALID = -1, /* argument outside its documented range           */
+  LBM_E_NOMEM = -2,   /* device or host allocation failed                */
+  LBM_E_CAP = -3,     /* request exceeds a capacity (server memory cap)  */
+  LBM_E_DEVICE = -4,  /* HIP runtime error                               */
+  LBM_E_NAN = -5,     /* non-finite values detected in the fields        */
+  LBM_E_STATE = -6    /* call out of order (e.g. step before init)       */
+};
+
+/* Storage of the distributions in HBM.  Computation is FP32 in all cases.
+ * *_DEV stores the deviation f_i - w_i rho_ref (and g_i - w_i T_ref).      */
+enum { LBM_STORE_F32 = 0, LBM_STORE_F32_DEV = 1, LBM_STORE_F16_DEV = 2, LBM_STORE_BF16_DEV = 3 };
+/* x boundaries: periodic, or velocity inlet at x = -1/convective outlet at x = nx. */
+enum { LBM_BCX_PERIODIC = 0, LBM_BCX_CHANNEL = 1 };
+/* y boundaries: periodic, or no-slip isothermal walls at y = -1 and y = ny. */
+enum { LBM_BCY_PERIODIC = 0, LBM_BCY_WALLS = 1 };
+enum { LBM_SIDE_S = 0, LBM_SIDE_N = 1 };
+
+/* Model and domain parameters (lbm_params_default fills the flow-boiling
+ * channel).  Rates s_e, s_eps, s_q <= 0 select the defaults s_e = s_eps =
+ * 1/tau_f and s_q = 8(2 - s_nu)/(8 - s_nu) (the value that makes the
+ * bounce-back wall exactly halfway for Poiseuille flow). */
+typedef struct {
+  int32_t nx, ny;       /* fluid nodes, >= 3 each                         */
+  int32_t storage;      /* LBM_STORE_*                                    */
+  int32_t bc_x, bc_y;   /* LBM_BCX_*, LBM_BCY_*                           */
+  int32_t isothermal;   /* 1: temperature frozen at T_iso, g not stored   */
+  int32_t single_phase; /* 1: Shan-Chen and adhesion forces off           */
+  int32_t reserved;
+  double a, b, R, omega;         /* Peng-Robinson constants, Eq. 12        */
+  double beta, c0, g;            /* Eq. 8 weighting, Eq. 11 c0, sign of G  */
+  double tau_f, s_e, s_eps, s_q; /* MRT: s_nu = 1/tau_f (Eq. 2 relation)   */
+  double tau_g, c_v;             /* Eq. 16 relaxation time, Eq. 19 c_v     */
+  double ga_x, ga_y;             /* buoyancy acceleration g_a, Eq. 14      */
+  double fb_x, fb_y;             /* constant body-force density            */
+  double u_in, T_in;             /* inlet velocity (|u_in| < 0.1) and temperature */
+  double U_out;                  /* convective-outlet speed (< 0: use u_in) */
+  double T_iso;                  /* temperature when isothermal            */
+  double rho_mid;                /* vapour threshold for diagnostics       */
+  double rho_ref, T_ref;         /* reference state of *_DEV storage       */
+} lbm_params;
+
+typedef struct lbm_domain lbm_domain;
+typedef struct lbm_batch lbm_batch;
+
+/* Diagnostics of one state, reduced in FP64 over the fluid nodes. */
+typedef struct {
+  int64_t step;        /* state index (number of completed steps)          */
+  double mass;         /* sum rho                                          */
+  double energy;       /* sum T                                            */
+  double heater_q;     /* sum over heater cells of 2 (T_wall - T(x, 0))     */
+  double vapor_cells;  /* number of nodes with rho < rho_mid               */
+  double psi_clamped;  /* nodes where p - rho/3 > 0 made psi imaginary     */
+  double nonfinite;    /* nodes with non-finite rho or T                   */
+  double p_in, p_out;  /* EOS pressure at (0, ny/2) and (nx-1, ny/2)       */
+} lbm_diag;
+
+const char* lbm_last_error(void);
+
+/* Fill p with the defaults (200x50 channel, PR constants of Sec. 2A). */
+int lbm_params_default(lbm_params* p);
+
+/* Device bytes a domain with these parameters needs (state buffers, outlet
+ * memory, wall maps, reductions and read-out fields). */
+int lbm_required_bytes(const lbm_params* p, size_t* bytes);
+
+/* Create a domain on the current HIP device.  Validates p (LBM_E_INVALID):
+ * nx, ny >= 3; tau_f, tau_g > 1/2; 0 < s_* < 2; c_v > 0; |u_in| < 0.1;
+ * temperatures > 0.  dev_mem/dev_bytes: see Conventions. */
+int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, size_t dev_bytes,
+               lbm_domain** out);
+int lbm_destroy(lbm_domain* d);
+
+/* Wall maps of one side (LBM_SIDE_S bottom, LBM_SIDE_N top), nx entries:
+ * wall temperature (anti-bounce-back value), false wall density rho_w of
+ * Eq. 15 (rho_w >= 0), heater flags (bottom side only, may be NULL) that
+ * select the cells summed in lbm_diag.heater_q.  Defaults: T_in, rho_w of a
+ * neutral wall is not assumed -- set both sides before lbm_init_fields when
+ * bc_y == LBM_BCY_WALLS. */
+int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, const double* rho_w,
+                      const int32_t* heater);
+
+/* Initial state: post-collision f = f^eq(rho0, 0), g = w_i T0 at every node,
+ * with rho0 = the array, or rho_uniform (1 + noise_rel * xi(x, y)) where xi
+ * in [-1, 1) is the SplitMix64 variate of seed ^ (y nx + x); T0 = the array
+ * or T_uniform.  Resets the step counter and the lagged mean density. */
+int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_uniform,
+                    double T_uniform, double noise_rel, uint64_t seed);
+
+/* Enqueue nsteps time steps on the domain's stream (nsteps >= 0). */
+int lbm_step(lbm_domain* d, int64_t nsteps);
+int lbm_sync(lbm_domain* d);
+int64_t lbm_step_count(const lbm_domain* d);
+
+/* Fields of the current state (post-streaming): rho, actual velocity u_act
+ * of Eq. 7, T.  Host FP64 arrays [ny][nx]; any pointer may be NULL. */
+int lbm_read_fields(lbm_domain* d, double* rho, double* ux, double* uy, double* T);
+/* Same fields into caller device buffers of nx*ny floats (no host copy). */
+int lbm_read_fields_device(lbm_domain* d, float* rho, float* ux, float* uy, float* T);
+
+/* Diagnostics of the current state. */
+int lbm_read_diag(lbm_domain* d, lbm_diag* out);
+/* Per-step diagnostics recorded on the device by lbm_step (ring of the last
+ * capacity states, oldest first).  *n receives the number written. */
+int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n);
+
+/* Checkpoint: state buffers, outlet memory, lagged means, step counter. */
+int lbm_save(lbm_domain* d, const char* path);
+int lbm_load(lbm_domain* d, const char* path);
+
+/* Maxwell equal-area coexistence of the Peng-Robinson EOS of p at T < Tc. */
+int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double* rho_v, double* p_sat);
+
+/* Rows per tile of the step kernel (>= 1; 0 restores the default). */
+int lbm_set_tile_rows(lbm_domain* d, int rows);
+
+/* Batched execution: n domains (all created on the same device, stepped
+ * together, one launch per step over the concatenated tile table, replayed
+ * from a captured hipGraph).  tune_cache_json may be NULL (no autotuning) or
+ * a path read/written by the autotuner. */
+int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune_cache_json, lbm_batch** out);
+int lbm_batch_step(lbm_batch* b, int64_t nsteps);
+int lbm_batch_sync(lbm_batch* b);
+int lbm_batch_destroy(lbm_batch* b);
+
+/* Plain device copy of bytes (HBM copy ceiling and counter calibration). */
+int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMFLOW_H */

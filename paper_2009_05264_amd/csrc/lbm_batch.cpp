@@ -1,0 +1,318 @@
+// Graph replay of single-domain stepping, batched execution of many domains
+// in one launch per step, and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmflow.h"
+#include "lbm_internal.h"
+#include "lbm_runtime.h"
+
+using namespace lbm;
+
+#define HIPCHECK(expr)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return lbm_fail(LBM_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+void lbm_drop_graphs(lbm_domain* d) {
+  for (auto& g : d->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  d->graphs.clear();
+}
+
+// Two launches (phase 0 then phase 1) captured once and replayed: the
+// kernels take everything that changes from step to step from device memory.
+static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int), void* ctx) {
+  HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc0 = enqueue(ctx, 0);
+  int rc1 = rc0 ? rc0 : enqueue(ctx, 1);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (rc0 || rc1) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc0 ? rc0 : rc1;
+  }
+  if (e != hipSuccess) return lbm_fail(LBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return lbm_fail(LBM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  g->graph = graph;
+  g->exec = exec;
+  return LBM_OK;
+}
+
+static int enqueue_domain_phase(void* ctx, int phase) {
+  lbm_domain* d = (lbm_domain*)ctx;
+  HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->grid, phase, d->stream));
+  return LBM_OK;
+}
+
+int lbm_run_steps(lbm_domain* d, int64_t n) {
+  if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch; step the batch");
+  if (n < 8) return lbm_enqueue_steps(d, n);
+  if ((d->step & 1) && n > 0) {
+    int rc = lbm_enqueue_steps(d, 1);
+    if (rc) return rc;
+    --n;
+  }
+  if (d->graphs.empty()) {
+    GraphEntry g;
+    int rc = capture_pair(d->stream, &g, enqueue_domain_phase, d);
+    if (rc) return rc;
+    d->graphs.push_back(g);
+  }
+  const int64_t pairs = n / 2;
+  for (int64_t k = 0; k < pairs; ++k) HIPCHECK(hipGraphLaunch(d->graphs[0].exec, d->stream));
+  d->step += 2 * pairs;
+  if (n & 1) return lbm_enqueue_steps(d, 1);
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ batches
+struct lbm_batch {
+  std::vector<lbm_domain*> doms;
+  hipStream_t stream = nullptr;
+  // one tile table per storage kind present in the batch
+  struct Group {
+    int storage;
+    Tile* tiles_d = nullptr;
+    int ntiles = 0;
+    int grid = 0;
+  };
+  std::vector<Group> groups;
+  GraphEntry graph;
+  int64_t k = 0;  // steps done by the batch
+  int rows = kDefaultTileRows;
+};
+
+// Tiles of each domain in its own layout, concatenated in the order of the
+// domains, grouped by storage kind.
+static int build_groups(lbm_batch* b) {
+  for (auto& g : b->groups)
+    if (g.tiles_d) (void)hipFree(g.tiles_d);
+  b->groups.clear();
+  std::map<int, std::vector<Tile>> by;
+  for (lbm_domain* d : b->doms) {
+    auto& v = by[d->P.storage];
+    v.insert(v.end(), d->tiles_h.begin(), d->tiles_h.end());
+  }
+  for (auto& kv : by) {
+    lbm_batch::Group g;
+    g.storage = kv.first;
+    g.ntiles = (int)kv.second.size();
+    HIPCHECK(hipMalloc(&g.tiles_d, g.ntiles * sizeof(Tile)));
+    HIPCHECK(hipMemcpy(g.tiles_d, kv.second.data(), g.ntiles * sizeof(Tile), hipMemcpyHostToDevice));
+    b->groups.push_back(g);
+  }
+  return LBM_OK;
+}
+
+static int enqueue_batch_phase(void* ctx, int phase) {
+  lbm_batch* b = (lbm_batch*)ctx;
+  for (auto& g : b->groups)
+    HIPCHECK(lbm_launch_step(g.storage, g.tiles_d, g.ntiles, g.grid, phase, b->stream));
+  return LBM_OK;
+}
+
+static void drop_batch_graph(lbm_batch* b) {
+  if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
+  if (b->graph.graph) (void)hipGraphDestroy(b->graph.graph);
+  b->graph = GraphEntry{};
+}
+
+// Retile every domain (rows per tile) keeping the pending reductions.
+static int retile(lbm_batch* b, int rows) {
+  for (lbm_domain* d : b->doms) {
+    d->in_batch = false;
+    int rc = lbm_set_tile_rows(d, rows);
+    d->in_batch = true;
+    if (rc) return rc;
+    // lbm_set_tile_rows re-uploads the descriptor with parity 0; restore it
+    d->host.parity = (int)((d->step - b->k) & 1);
+    HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
+  }
+  b->rows = rows;
+  return build_groups(b);
+}
+
+static int batch_steps_plain(lbm_batch* b, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) {
+    int rc = enqueue_batch_phase(b, (int)((b->k + i) & 1));
+    if (rc) return rc;
+  }
+  b->k += n;
+  for (lbm_domain* d : b->doms) d->step += n;
+  return LBM_OK;
+}
+
+// Mean time of one step of the batch over `reps` graph pairs (steps are real).
+static int time_config(lbm_batch* b, int reps, float* ms) {
+  drop_batch_graph(b);
+  if (b->k & 1) {
+    int rc = batch_steps_plain(b, 1);
+    if (rc) return rc;
+  }
+  int rc = capture_pair(b->stream, &b->graph, enqueue_batch_phase, b);
+  if (rc) return rc;
+  HIPCHECK(hipGraphLaunch(b->graph.exec, b->stream));  // warm-up pair
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  HIPCHECK(hipEventRecord(e0, b->stream));
+  for (int r = 0; r < reps; ++r) HIPCHECK(hipGraphLaunch(b->graph.exec, b->stream));
+  HIPCHECK(hipEventRecord(e1, b->stream));
+  HIPCHECK(hipEventSynchronize(e1));
+  float t = 0;
+  HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int64_t done = 2 * (reps + 1);
+  b->k += done;
+  for (lbm_domain* d : b->doms) d->step += done;
+  *ms = t / (2.0f * reps);
+  return LBM_OK;
+}
+
+static std::string batch_key(const lbm_batch* b) {
+  std::ostringstream os;
+  long long nodes = 0;
+  for (lbm_domain* d : b->doms) nodes += (long long)d->P.nx * d->P.ny;
+  os << "n" << b->doms.size() << "_nodes" << nodes;
+  return os.str();
+}
+
+// Autotuner: rows per tile x workgroups per launch, measured on the batch
+// itself; the winner is cached per batch signature in a small text file.
+static int autotune(lbm_batch* b, const char* cache) {
+  const std::string key = batch_key(b);
+  if (cache) {
+    std::ifstream in(cache);
+    std::string k;
+    int rows, gridmul;
+    while (in >> k >> rows >> gridmul) {
+      if (k == key) {
+        int rc = retile(b, rows);
+        if (rc) return rc;
+        for (auto& g : b->groups) g.grid = gridmul > 0 ? std::min(g.ntiles, 256 * gridmul) : 0;
+        return LBM_OK;
+      }
+    }
+  }
+  const int row_opts[] = {16, 32, 64, 128};
+  const int grid_opts[] = {0, 8, 16};
+  float best = 1e30f;
+  int brow = kDefaultTileRows, bgrid = 0;
+  for (int rows : row_opts) {
+    int rc = retile(b, rows);
+    if (rc) return rc;
+    for (int gm : grid_opts) {
+      for (auto& g : b->groups) g.grid = gm > 0 ? std::min(g.ntiles, 256 * gm) : 0;
+      float ms = 0;
+      rc = time_config(b, 10, &ms);
+      if (rc) return rc;
+      if (ms < best) {
+        best = ms;
+        brow = rows;
+        bgrid = gm;
+      }
+    }
+  }
+  int rc = retile(b, brow);
+  if (rc) return rc;
+  for (auto& g : b->groups) g.grid = bgrid > 0 ? std::min(g.ntiles, 256 * bgrid) : 0;
+  drop_batch_graph(b);
+  if (cache) {
+    std::ofstream out(cache, std::ios::app);
+    out << key << " " << brow << " " << bgrid << "\n";
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune_cache_json,
+                                lbm_batch** out) {
+  if (!doms || n <= 0 || !out) return lbm_fail(LBM_E_INVALID, "bad batch arguments");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!doms[i]) return lbm_fail(LBM_E_INVALID, "domain %d is NULL", i);
+    if (!doms[i]->inited) return lbm_fail(LBM_E_STATE, "domain %d is not initialised", i);
+    if (doms[i]->in_batch) return lbm_fail(LBM_E_STATE, "domain %d already belongs to a batch", i);
+    for (int j = 0; j < i; ++j)
+      if (doms[j] == doms[i]) return lbm_fail(LBM_E_INVALID, "domain %d appears twice", i);
+  }
+  lbm_batch* b = new lbm_batch();
+  b->stream = doms[0]->stream;
+  for (int i = 0; i < n; ++i) {
+    HIPCHECK(hipStreamSynchronize(doms[i]->stream));
+    b->doms.push_back(doms[i]);
+  }
+  for (lbm_domain* d : b->doms) {
+    d->in_batch = true;
+    d->host.parity = (int)(d->step & 1);
+    HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
+  }
+  int rc = build_groups(b);
+  if (!rc && tune_cache_json) rc = autotune(b, tune_cache_json[0] ? tune_cache_json : nullptr);
+  if (rc) {
+    lbm_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+extern "C" int lbm_batch_step(lbm_batch* b, int64_t n) {
+  if (!b) return lbm_fail(LBM_E_INVALID, "batch is NULL");
+  if (n < 0) return lbm_fail(LBM_E_INVALID, "nsteps must be >= 0");
+  if (n < 8) return batch_steps_plain(b, n);
+  if (b->k & 1) {
+    int rc = batch_steps_plain(b, 1);
+    if (rc) return rc;
+    --n;
+  }
+  if (!b->graph.exec) {
+    int rc = capture_pair(b->stream, &b->graph, enqueue_batch_phase, b);
+    if (rc) return rc;
+  }
+  const int64_t pairs = n / 2;
+  for (int64_t i = 0; i < pairs; ++i) HIPCHECK(hipGraphLaunch(b->graph.exec, b->stream));
+  b->k += 2 * pairs;
+  for (lbm_domain* d : b->doms) d->step += 2 * pairs;
+  if (n & 1) return batch_steps_plain(b, 1);
+  return LBM_OK;
+}
+
+extern "C" int lbm_batch_sync(lbm_batch* b) {
+  if (!b) return lbm_fail(LBM_E_INVALID, "batch is NULL");
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_batch_graph(b);
+  for (auto& g : b->groups)
+    if (g.tiles_d) (void)hipFree(g.tiles_d);
+  for (lbm_domain* d : b->doms) {
+    d->in_batch = false;
+    d->host.parity = 0;
+    (void)hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice);
+  }
+  delete b;
+  return LBM_OK;
+}

@@ -1,0 +1,79 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kStripInterior = 60;  // interior columns per wave (64 - 2 - 2 halo)
+constexpr int kPartials = 8;        // doubles per tile partial
+constexpr int kRing = 4096;         // per-step diagnostics records kept on device
+
+// Partial sums of one tile, in this order.
+enum { P_MASS = 0, P_ENERGY, P_HEATQ, P_VAPOR, P_CLAMP, P_NONFINITE, P_PIN, P_POUT };
+
+// One diagnostics record (same layout as lbm_diag).
+struct DiagRec {
+  long long step;
+  double v[kPartials];
+};
+
+// Device-resident descriptor of one domain.  All physics constants are
+// pre-converted to float on the host.
+struct DevDomain {
+  int nx, ny, pitch, storage;
+  int bc_x, bc_y, isothermal, single_phase;
+  long long plane;  // elements per distribution plane (pitch * ny)
+  int ntiles, pad0;
+  // EOS / force constants
+  float a, b, R, kappa;
+  float inv_Tc, Tc, beta, c0g2;   // c0g2 = 2 / (c0 g)
+  float G1, G2, half_1mb, pad1;    // half_1mb = (1 - beta) / 2
+  // collision
+  float s_e, s_eps, s_q, s_nu;
+  float omega_g, inv_cv, pad2, pad3;
+  float ga_x, ga_y, fb_x, fb_y;
+  float u_in, T_in, U_out, inv_1pU;  // inv_1pU = 1 / (1 + U_out)
+  float in_geq;                      // T_in (1 + 3 u_in^2): inlet anti-bounce-back state
+  float rho_ref, T_ref, T_iso, rho_mid;
+  float pad4[3];
+  // buffers
+  void* buf[2];         // state A/B: 9 f planes then 9 g planes (g absent when isothermal)
+  float* fold[2];       // convective-outlet memory [3][ny] (deviation form), A/B
+  const float* psiw[2]; // pseudopotential of the false wall density, S and N, [nx]
+  const float* Tw[2];   // wall temperature, S and N, [nx]
+  const int* heater;    // bottom heater flags [nx]
+  double* partials[2];  // [ntiles][kPartials], A/B
+  double* rbar;         // [2] lagged mean density slots
+  DiagRec* ring;        // [kRing]
+  long long* step_dev;  // device step counter (written only by the first tile)
+  double* readout_partials;  // [ntiles][kPartials]
+  float* out[4];        // read-out fields rho, ux, uy, T [ny][nx]
+  int parity;           // storage buffer parity offset
+  int pad5;
+};
+
+// One tile of the step kernel: a 64-lane strip starting two columns left of
+// x0, covering rows [y0, y1).
+struct Tile {
+  DevDomain* d;
+  int x0, y0, y1;
+  int local;  // tile index within its domain (partials slot); 0 = first tile
+};
+
+enum StepMode { MODE_STEP = 0, MODE_READOUT = 1 };
+
+}  // namespace lbm
+
+// Launch wrappers (lbm_kernels.hip).
+hipError_t lbm_launch_step(int storage, const lbm::Tile* tiles, int ntiles, int grid, int phase,
+                           hipStream_t s);
+hipError_t lbm_launch_readout(int storage, const lbm::Tile* tiles, int ntiles, int phase,
+                              hipStream_t s);
+hipError_t lbm_launch_finalize(lbm::DevDomain* d, const double* partials, int ntiles, double* out8,
+                               hipStream_t s);
+hipError_t lbm_launch_init(int storage, lbm::DevDomain* dhost_copy_dev, const lbm::DevDomain& dh,
+                           const double* rho0, const double* T0, double rho_u, double T_u,
+                           double noise, unsigned long long seed, int buf_index, hipStream_t s);
+hipError_t lbm_launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -1,0 +1,753 @@
+// Host runtime of the C ABI declared in include/lbmflow.h: parameter
+// validation, device memory layout, wall maps, initial state, stepping,
+// read-out, diagnostics, checkpoints and the Maxwell helper.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmflow.h"
+#include "lbm_internal.h"
+#include "lbm_runtime.h"
+
+using namespace lbm;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+int lbm_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHECK(expr)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return lbm_fail(LBM_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+extern "C" const char* lbm_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ physics helpers (host, FP64)
+namespace {
+
+double crit_T(const lbm_params& p) { return 0.0778 * p.a / (0.45724 * p.b * p.R); }
+double kappa_of(const lbm_params& p) {
+  return 0.37464 + 1.54226 * p.omega - 0.26992 * p.omega * p.omega;
+}
+// Peng-Robinson pressure (Eq. 12).
+double pr_p(const lbm_params& P, double rho, double T) {
+  const double s = std::sqrt(T / crit_T(P));
+  const double sa = 1.0 + kappa_of(P) * (1.0 - s);
+  return rho * P.R * T / (1.0 - P.b * rho) -
+         P.a * sa * sa * rho * rho / (1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho);
+}
+// Pseudopotential (Eq. 11) at (rho, T), 0 where p - rho/3 has the wrong sign.
+double pr_psi(const lbm_params& P, double rho, double T) {
+  const double q = 2.0 * (pr_p(P, rho, T) - rho / 3.0) / (P.c0 * P.g);
+  return q > 0.0 ? std::sqrt(q) : 0.0;
+}
+
+unsigned long long splitmix64_host(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int rates(const lbm_params& p, double* s_nu, double* s_e, double* s_eps, double* s_q) {
+  *s_nu = 1.0 / p.tau_f;
+  *s_e = p.s_e > 0 ? p.s_e : *s_nu;
+  *s_eps = p.s_eps > 0 ? p.s_eps : *s_nu;
+  *s_q = p.s_q > 0 ? p.s_q : 8.0 * (2.0 - *s_nu) / (8.0 - *s_nu);
+  return 0;
+}
+
+int validate(const lbm_params* p) {
+  if (!p) return lbm_fail(LBM_E_INVALID, "params is NULL");
+  if (p->nx < 3 || p->ny < 3 || p->nx > 32767 || p->ny > 32767)
+    return lbm_fail(LBM_E_INVALID, "nx, ny must lie in [3, 32767] (got %d x %d)", p->nx, p->ny);
+  if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16_DEV)
+    return lbm_fail(LBM_E_INVALID, "unknown storage %d", p->storage);
+  if ((p->bc_x != LBM_BCX_PERIODIC && p->bc_x != LBM_BCX_CHANNEL) ||
+      (p->bc_y != LBM_BCY_PERIODIC && p->bc_y != LBM_BCY_WALLS))
+    return lbm_fail(LBM_E_INVALID, "unknown boundary kind");
+  if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5))
+    return lbm_fail(LBM_E_INVALID, "tau_f and tau_g must exceed 1/2");
+  double sn, se, sp, sq;
+  rates(*p, &sn, &se, &sp, &sq);
+  if (!(se > 0 && se < 2) || !(sp > 0 && sp < 2) || !(sq > 0 && sq < 2))
+    return lbm_fail(LBM_E_INVALID, "MRT rates must lie in (0, 2)");
+  if (!(p->c_v > 0)) return lbm_fail(LBM_E_INVALID, "c_v must be positive");
+  if (!(std::fabs(p->u_in) < 0.1)) return lbm_fail(LBM_E_INVALID, "|u_in| must be < 0.1");
+  if (!(p->T_in > 0) || !(p->T_iso > 0))
+    return lbm_fail(LBM_E_INVALID, "temperatures must be positive");
+  if (!(p->a > 0) || !(p->b > 0) || !(p->R > 0) || !(p->c0 > 0) || p->g == 0)
+    return lbm_fail(LBM_E_INVALID, "EOS constants out of range");
+  if (p->bc_x == LBM_BCX_CHANNEL && p->nx < 3)
+    return lbm_fail(LBM_E_INVALID, "a channel needs nx >= 3");
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ layout
+namespace {
+
+struct Layout {
+  size_t state, fold, psiw, Tw, heater, partials, rpart, rbar, ring, stepc, out, desc, tiles, total;
+  size_t state_bytes, fold_bytes;
+};
+
+int pitch_of(int nx) { return (nx + 31) / 32 * 32; }
+int elem_bytes(int storage) { return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV ? 2 : 4; }
+int max_tiles(const lbm_params& p) {
+  const int strips = (p.nx + kStripInterior - 1) / kStripInterior;
+  return strips * ((p.ny + kMinTileRows - 1) / kMinTileRows);
+}
+
+Layout layout_of(const lbm_params& p) {
+  Layout L{};
+  const size_t planes = p.isothermal ? 9 : 18;
+  const size_t plane = (size_t)pitch_of(p.nx) * p.ny;
+  L.state_bytes = align_up(planes * plane * elem_bytes(p.storage), 256);
+  L.fold_bytes = align_up(3 * (size_t)p.ny * sizeof(float), 256);
+  const size_t mt = max_tiles(p);
+  size_t o = 0;
+  L.state = o; o += 2 * L.state_bytes;
+  L.fold = o; o += 2 * L.fold_bytes;
+  L.psiw = o; o += 2 * align_up(p.nx * sizeof(float), 256);
+  L.Tw = o; o += 2 * align_up(p.nx * sizeof(float), 256);
+  L.heater = o; o += align_up(p.nx * sizeof(int), 256);
+  L.partials = o; o += 2 * align_up(mt * kPartials * sizeof(double), 256);
+  L.rpart = o; o += align_up(mt * kPartials * sizeof(double), 256);
+  L.rbar = o; o += 256;
+  L.ring = o; o += align_up(kRing * sizeof(DiagRec), 256);
+  L.stepc = o; o += 256;
+  L.out = o; o += 4 * align_up((size_t)p.nx * p.ny * sizeof(float), 256);
+  L.desc = o; o += align_up(sizeof(DevDomain), 256);
+  L.tiles = o; o += align_up(mt * sizeof(Tile), 256);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ API
+extern "C" int lbm_params_default(lbm_params* p) {
+  if (!p) return lbm_fail(LBM_E_INVALID, "params is NULL");
+  memset(p, 0, sizeof(*p));
+  p->nx = 200;
+  p->ny = 50;
+  p->storage = LBM_STORE_F32;
+  p->bc_x = LBM_BCX_CHANNEL;
+  p->bc_y = LBM_BCY_WALLS;
+  p->a = 2.0 / 49.0;
+  p->b = 2.0 / 21.0;
+  p->R = 1.0;
+  p->omega = 0.344;
+  p->beta = 1.16;
+  p->c0 = 6.0;
+  p->g = -1.0;
+  p->tau_f = 1.0;
+  p->s_e = p->s_eps = p->s_q = 0.0;
+  p->tau_g = 0.6;
+  p->c_v = 6.0;
+  p->ga_x = 0.0;
+  p->ga_y = -5e-5;
+  const double Tc = crit_T(*p);
+  const double Ts = 0.86 * Tc;
+  p->u_in = 0.005;
+  p->T_in = 0.95 * Ts;
+  p->U_out = -1.0;
+  p->T_iso = Ts;
+  p->rho_mid = 0.5 * (6.4989457632878835 + 0.3796789993997205);
+  p->rho_ref = 0.0;
+  p->T_ref = 0.0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_required_bytes(const lbm_params* p, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) return lbm_fail(LBM_E_INVALID, "bytes is NULL");
+  *bytes = layout_of(*p).total;
+  return LBM_OK;
+}
+
+namespace {
+
+void fill_desc(lbm_domain* d) {
+  const lbm_params& p = d->P;
+  DevDomain& D = d->host;
+  const double Tc = crit_T(p);
+  double s_nu, s_e, s_eps, s_q;
+  rates(p, &s_nu, &s_e, &s_eps, &s_q);
+  D.nx = p.nx;
+  D.ny = p.ny;
+  D.pitch = pitch_of(p.nx);
+  D.storage = p.storage;
+  D.bc_x = p.bc_x;
+  D.bc_y = p.bc_y;
+  D.isothermal = p.isothermal;
+  D.single_phase = p.single_phase;
+  D.plane = (long long)D.pitch * p.ny;
+  D.a = (float)p.a;
+  D.b = (float)p.b;
+  D.R = (float)p.R;
+  D.kappa = (float)kappa_of(p);
+  D.inv_Tc = (float)(1.0 / Tc);
+  D.Tc = (float)Tc;
+  D.beta = (float)p.beta;
+  D.c0g2 = (float)(2.0 / (p.c0 * p.g));
+  D.G1 = (float)(2.0 * p.g);
+  D.G2 = (float)(0.5 * p.g);
+  D.half_1mb = (float)(0.5 * (1.0 - p.beta));
+  D.s_e = (float)s_e;
+  D.s_eps = (float)s_eps;
+  D.s_q = (float)s_q;
+  D.s_nu = (float)s_nu;
+  D.omega_g = (float)(1.0 / p.tau_g);
+  D.inv_cv = (float)(1.0 / p.c_v);
+  D.ga_x = (float)p.ga_x;
+  D.ga_y = (float)p.ga_y;
+  D.fb_x = (float)p.fb_x;
+  D.fb_y = (float)p.fb_y;
+  D.u_in = (float)p.u_in;
+  D.T_in = (float)p.T_in;
+  const double U = p.U_out >= 0 ? p.U_out : p.u_in;
+  D.U_out = (float)U;
+  D.inv_1pU = (float)(1.0 / (1.0 + U));
+  D.in_geq = (float)(p.T_in * (1.0 + 3.0 * p.u_in * p.u_in));
+  D.rho_ref = (float)p.rho_ref;
+  D.T_ref = (float)p.T_ref;
+  D.T_iso = (float)p.T_iso;
+  D.rho_mid = (float)p.rho_mid;
+}
+
+}  // namespace
+
+int lbm_build_tiles(lbm_domain* d) {
+  lbm_drop_graphs(d);
+  const int nx = d->P.nx, ny = d->P.ny;
+  const int rows = std::max(kMinTileRows, d->rows);
+  const int strips = (nx + kStripInterior - 1) / kStripInterior;
+  const int segs = (ny + rows - 1) / rows;
+  d->tiles_h.clear();
+  for (int s = 0; s < segs; ++s)
+    for (int t = 0; t < strips; ++t) {
+      Tile tl;
+      tl.d = d->dev;
+      tl.x0 = t * kStripInterior;
+      tl.y0 = s * rows;
+      tl.y1 = std::min(ny, tl.y0 + rows);
+      tl.local = (int)d->tiles_h.size();
+      d->tiles_h.push_back(tl);
+    }
+  d->ntiles = (int)d->tiles_h.size();
+  d->host.ntiles = d->ntiles;
+  HIPCHECK(hipMemcpyAsync(d->tiles_d, d->tiles_h.data(), d->ntiles * sizeof(Tile),
+                          hipMemcpyHostToDevice, d->stream));
+  HIPCHECK(hipMemcpyAsync(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, size_t dev_bytes,
+                          lbm_domain** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return lbm_fail(LBM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  const Layout L = layout_of(*p);
+  if (dev_mem && dev_bytes < L.total)
+    return lbm_fail(LBM_E_INVALID, "caller buffer of %zu bytes is smaller than the %zu required",
+                    dev_bytes, L.total);
+  if (dev_mem && ((uintptr_t)dev_mem & 255))
+    return lbm_fail(LBM_E_INVALID, "caller buffer must be 256-byte aligned");
+  lbm_domain* d = new (std::nothrow) lbm_domain();
+  if (!d) return lbm_fail(LBM_E_NOMEM, "host allocation failed");
+  d->P = *p;
+  d->rows = kDefaultTileRows;
+  if (hip_stream) {
+    d->stream = (hipStream_t)hip_stream;
+    d->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete d;
+      return lbm_fail(LBM_E_DEVICE, "hipStreamCreate failed");
+    }
+    d->own_stream = true;
+  }
+  if (dev_mem) {
+    d->mem = (char*)dev_mem;
+    d->own_mem = false;
+  } else {
+    void* m = nullptr;
+    if (hipMalloc(&m, L.total) != hipSuccess) {
+      if (d->own_stream) (void)hipStreamDestroy(d->stream);
+      delete d;
+      return lbm_fail(LBM_E_NOMEM, "hipMalloc of %zu bytes failed", L.total);
+    }
+    d->mem = (char*)m;
+    d->own_mem = true;
+  }
+  d->bytes = L.total;
+  char* m = d->mem;
+  fill_desc(d);
+  DevDomain& D = d->host;
+  D.buf[0] = m + L.state;
+  D.buf[1] = m + L.state + L.state_bytes;
+  D.fold[0] = (float*)(m + L.fold);
+  D.fold[1] = (float*)(m + L.fold + L.fold_bytes);
+  const size_t mb = align_up(p->nx * sizeof(float), 256);
+  d->psiw_d[0] = (float*)(m + L.psiw);
+  d->psiw_d[1] = (float*)(m + L.psiw + mb);
+  d->Tw_d[0] = (float*)(m + L.Tw);
+  d->Tw_d[1] = (float*)(m + L.Tw + mb);
+  D.psiw[0] = d->psiw_d[0];
+  D.psiw[1] = d->psiw_d[1];
+  D.Tw[0] = d->Tw_d[0];
+  D.Tw[1] = d->Tw_d[1];
+  d->heater_d = (int*)(m + L.heater);
+  D.heater = d->heater_d;
+  const size_t pb = align_up(max_tiles(*p) * kPartials * sizeof(double), 256);
+  D.partials[0] = (double*)(m + L.partials);
+  D.partials[1] = (double*)(m + L.partials + pb);
+  D.readout_partials = (double*)(m + L.rpart);
+  D.rbar = (double*)(m + L.rbar);
+  D.ring = (DiagRec*)(m + L.ring);
+  D.step_dev = (long long*)(m + L.stepc);
+  const size_t ob = align_up((size_t)p->nx * p->ny * sizeof(float), 256);
+  for (int k = 0; k < 4; ++k) D.out[k] = (float*)(m + L.out + k * ob);
+  D.parity = 0;
+  d->dev = (DevDomain*)(m + L.desc);
+  d->tiles_d = (Tile*)(m + L.tiles);
+  // default walls: inlet temperature, neutral wall (rho_w = rho of the initial
+  // uniform state is not known here -> zero pseudopotential until set)
+  std::vector<float> z(p->nx, 0.f), tw(p->nx, (float)p->T_in);
+  std::vector<int> hz(p->nx, 0);
+  for (int s = 0; s < 2; ++s) {
+    if (hipMemcpy(d->psiw_d[s], z.data(), p->nx * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->Tw_d[s], tw.data(), p->nx * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      lbm_destroy(d);
+      return lbm_fail(LBM_E_DEVICE, "map upload failed");
+    }
+  }
+  d->heater_h.assign(p->nx, 0);
+  d->Tw_h[0].assign(p->nx, p->T_in);
+  d->Tw_h[1].assign(p->nx, p->T_in);
+  if (hipMemcpy(d->heater_d, hz.data(), p->nx * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    lbm_destroy(d);
+    return lbm_fail(LBM_E_DEVICE, "map upload failed");
+  }
+  rc = lbm_build_tiles(d);
+  if (rc) {
+    lbm_destroy(d);
+    return rc;
+  }
+  *out = d;
+  return LBM_OK;
+}
+
+extern "C" int lbm_destroy(lbm_domain* d) {
+  if (!d) return LBM_OK;
+  if (d->stream) (void)hipStreamSynchronize(d->stream);
+  lbm_drop_graphs(d);
+  if (d->own_mem && d->mem) (void)hipFree(d->mem);
+  if (d->own_stream && d->stream) (void)hipStreamDestroy(d->stream);
+  delete d;
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, const double* rho_w,
+                                 const int32_t* heater) {
+  if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  if (side != LBM_SIDE_S && side != LBM_SIDE_N) return lbm_fail(LBM_E_INVALID, "bad side %d", side);
+  if (!T_wall || !rho_w) return lbm_fail(LBM_E_INVALID, "T_wall and rho_w are required");
+  const int nx = d->P.nx;
+  std::vector<float> ps(nx), tw(nx);
+  for (int x = 0; x < nx; ++x) {
+    if (!(rho_w[x] >= 0) || !(T_wall[x] > 0))
+      return lbm_fail(LBM_E_INVALID, "rho_w >= 0 and T_wall > 0 required (x = %d)", x);
+    ps[x] = (float)pr_psi(d->P, rho_w[x], T_wall[x]);
+    tw[x] = (float)T_wall[x];
+    d->Tw_h[side][x] = T_wall[x];
+  }
+  HIPCHECK(hipMemcpyAsync(d->psiw_d[side], ps.data(), nx * sizeof(float), hipMemcpyHostToDevice, d->stream));
+  HIPCHECK(hipMemcpyAsync(d->Tw_d[side], tw.data(), nx * sizeof(float), hipMemcpyHostToDevice, d->stream));
+  if (side == LBM_SIDE_S) {
+    std::vector<int> h(nx, 0);
+    if (heater)
+      for (int x = 0; x < nx; ++x) h[x] = heater[x] ? 1 : 0;
+    d->heater_h = h;
+    HIPCHECK(hipMemcpyAsync(d->heater_d, h.data(), nx * sizeof(int), hipMemcpyHostToDevice, d->stream));
+  }
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_u,
+                               double T_u, double noise, uint64_t seed) {
+  if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  const int nx = d->P.nx, ny = d->P.ny;
+  const size_t n = (size_t)nx * ny;
+  if (!rho0 && !(rho_u > 0)) return lbm_fail(LBM_E_INVALID, "rho_uniform must be positive");
+  if (!T0 && !(T_u > 0)) return lbm_fail(LBM_E_INVALID, "T_uniform must be positive");
+  double* rd = nullptr;
+  double* td = nullptr;
+  // mean of the initial density (FP64, fixed order)
+  double sum = 0.0;
+  if (rho0) {
+    for (size_t i = 0; i < n; ++i) sum += rho0[i];
+  } else {
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const unsigned long long z = splitmix64_host(seed ^ (unsigned long long)((long long)y * nx + x));
+        const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        sum += rho_u * (1.0 + noise * (2.0 * u - 1.0));
+      }
+  }
+  if (rho0) {
+    HIPCHECK(hipMalloc(&rd, n * sizeof(double)));
+    HIPCHECK(hipMemcpy(rd, rho0, n * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (T0) {
+    HIPCHECK(hipMalloc(&td, n * sizeof(double)));
+    HIPCHECK(hipMemcpy(td, T0, n * sizeof(double), hipMemcpyHostToDevice));
+  }
+  d->host.parity = 0;
+  HIPCHECK(hipMemcpyAsync(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
+  HIPCHECK(lbm_launch_init(d->P.storage, d->dev, d->host, rd, td, rho_u, T_u, noise, seed, 0, d->stream));
+  // lagged means and the partial sums the first step finalizes
+  const double mean = sum / (double)n;
+  double rb[2] = {mean, mean};
+  HIPCHECK(hipMemcpyAsync(d->host.rbar, rb, sizeof(rb), hipMemcpyHostToDevice, d->stream));
+  std::vector<double> parts((size_t)d->ntiles * kPartials, 0.0);
+  parts[P_MASS] = sum;
+  HIPCHECK(hipMemcpyAsync(d->host.partials[1], parts.data(), parts.size() * sizeof(double),
+                          hipMemcpyHostToDevice, d->stream));
+  long long zero = 0;
+  HIPCHECK(hipMemcpyAsync(d->host.step_dev, &zero, sizeof(zero), hipMemcpyHostToDevice, d->stream));
+  HIPCHECK(hipMemsetAsync(d->host.ring, 0xFF, kRing * sizeof(DiagRec), d->stream));
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  if (rd) (void)hipFree(rd);
+  if (td) (void)hipFree(td);
+  d->step = 0;
+  d->inited = true;
+  return LBM_OK;
+}
+
+int lbm_enqueue_steps(lbm_domain* d, int64_t nsteps) {
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int phase = (int)((d->step + k) & 1) ^ d->host.parity;
+    HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->grid, phase, d->stream));
+  }
+  d->step += nsteps;
+  return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_domain* d, int64_t nsteps) {
+  if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  if (!d->inited) return lbm_fail(LBM_E_STATE, "lbm_init_fields has not been called");
+  if (nsteps < 0) return lbm_fail(LBM_E_INVALID, "nsteps must be >= 0");
+  return lbm_run_steps(d, nsteps);
+}
+
+extern "C" int lbm_sync(lbm_domain* d) {
+  if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  return LBM_OK;
+}
+
+extern "C" int64_t lbm_step_count(const lbm_domain* d) { return d ? d->step : -1; }
+
+static int readout(lbm_domain* d) {
+  if (!d->inited) return lbm_fail(LBM_E_STATE, "lbm_init_fields has not been called");
+  // the kernel adds the descriptor's parity: pass the phase that lands on step & 1
+  HIPCHECK(lbm_launch_readout(d->P.storage, d->tiles_d, d->ntiles,
+                              (int)(d->step & 1) ^ d->host.parity, d->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_read_fields_device(lbm_domain* d, float* rho, float* ux, float* uy, float* T) {
+  if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  int rc = readout(d);
+  if (rc) return rc;
+  const size_t n = (size_t)d->P.nx * d->P.ny;
+  float* dsts[4] = {rho, ux, uy, T};
+  for (int k = 0; k < 4; ++k)
+    if (dsts[k])
+      HIPCHECK(hipMemcpyAsync(dsts[k], d->host.out[k], n * sizeof(float), hipMemcpyDeviceToDevice, d->stream));
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_read_fields(lbm_domain* d, double* rho, double* ux, double* uy, double* T) {
+  if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  int rc = readout(d);
+  if (rc) return rc;
+  const size_t n = (size_t)d->P.nx * d->P.ny;
+  std::vector<float> tmp(n);
+  double* dsts[4] = {rho, ux, uy, T};
+  for (int k = 0; k < 4; ++k) {
+    if (!dsts[k]) continue;
+    HIPCHECK(hipMemcpyAsync(tmp.data(), d->host.out[k], n * sizeof(float), hipMemcpyDeviceToHost, d->stream));
+    HIPCHECK(hipStreamSynchronize(d->stream));
+    for (size_t i = 0; i < n; ++i) dsts[k][i] = tmp[i];
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_read_diag(lbm_domain* d, lbm_diag* out) {
+  if (!d || !out) return lbm_fail(LBM_E_INVALID, "NULL argument");
+  int rc = readout(d);
+  if (rc) return rc;
+  double* res = (double*)(d->host.rbar) + 16;  // scratch inside the 256-byte rbar block
+  HIPCHECK(lbm_launch_finalize(d->dev, d->host.readout_partials, d->ntiles, res, d->stream));
+  double h[kPartials];
+  HIPCHECK(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  out->step = d->step;
+  out->mass = h[P_MASS];
+  out->energy = h[P_ENERGY];
+  out->heater_q = h[P_HEATQ];
+  out->vapor_cells = h[P_VAPOR];
+  out->psi_clamped = h[P_CLAMP];
+  out->nonfinite = h[P_NONFINITE];
+  out->p_in = h[P_PIN];
+  out->p_out = h[P_POUT];
+  return LBM_OK;
+}
+
+extern "C" int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n) {
+  if (!d || !out || !n) return lbm_fail(LBM_E_INVALID, "NULL argument");
+  std::vector<DiagRec> ring(kRing);
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  HIPCHECK(hipMemcpy(ring.data(), d->host.ring, kRing * sizeof(DiagRec), hipMemcpyDeviceToHost));
+  std::vector<DiagRec> valid;
+  for (auto& r : ring)
+    if (r.step >= 0) valid.push_back(r);
+  std::sort(valid.begin(), valid.end(), [](const DiagRec& a, const DiagRec& b) { return a.step < b.step; });
+  const int k = std::min<int>(max, (int)valid.size());
+  const int off = (int)valid.size() - k;
+  for (int i = 0; i < k; ++i) {
+    const DiagRec& r = valid[off + i];
+    out[i].step = r.step;
+    out[i].mass = r.v[P_MASS];
+    out[i].energy = r.v[P_ENERGY];
+    out[i].heater_q = r.v[P_HEATQ];
+    out[i].vapor_cells = r.v[P_VAPOR];
+    out[i].psi_clamped = r.v[P_CLAMP];
+    out[i].nonfinite = r.v[P_NONFINITE];
+    out[i].p_in = r.v[P_PIN];
+    out[i].p_out = r.v[P_POUT];
+  }
+  *n = k;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ checkpoints
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int32_t nx, ny, storage, isothermal;
+  int64_t step;
+  uint64_t state_bytes, fold_bytes, part_bytes;
+};
+}  // namespace
+
+extern "C" int lbm_save(lbm_domain* d, const char* path) {
+  if (!d || !path) return lbm_fail(LBM_E_INVALID, "NULL argument");
+  if (!d->inited) return lbm_fail(LBM_E_STATE, "nothing to save");
+  const Layout L = layout_of(d->P);
+  const int ph = (int)(d->step & 1);
+  const size_t pb = (size_t)d->ntiles * kPartials * sizeof(double);
+  std::vector<char> st(L.state_bytes), fo(L.fold_bytes), pa(pb);
+  double rb[2];
+  long long sd;
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  HIPCHECK(hipMemcpy(st.data(), d->host.buf[ph], L.state_bytes, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(fo.data(), d->host.fold[ph], L.fold_bytes, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(pa.data(), d->host.partials[ph ^ 1], pb, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(rb, d->host.rbar, sizeof(rb), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(&sd, d->host.step_dev, sizeof(sd), hipMemcpyDeviceToHost));
+  FILE* f = fopen(path, "wb");
+  if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s for writing", path);
+  CkptHeader h{};
+  memcpy(h.magic, "LBMCKPT1", 8);
+  h.nx = d->P.nx;
+  h.ny = d->P.ny;
+  h.storage = d->P.storage;
+  h.isothermal = d->P.isothermal;
+  h.step = d->step;
+  h.state_bytes = L.state_bytes;
+  h.fold_bytes = L.fold_bytes;
+  h.part_bytes = pb;
+  bool ok = fwrite(&h, sizeof(h), 1, f) == 1 && fwrite(st.data(), 1, st.size(), f) == st.size() &&
+            fwrite(fo.data(), 1, fo.size(), f) == fo.size() && fwrite(pa.data(), 1, pa.size(), f) == pa.size() &&
+            fwrite(rb, sizeof(rb), 1, f) == 1 && fwrite(&sd, sizeof(sd), 1, f) == 1;
+  ok = (fclose(f) == 0) && ok;
+  return ok ? LBM_OK : lbm_fail(LBM_E_INVALID, "write to %s failed", path);
+}
+
+extern "C" int lbm_load(lbm_domain* d, const char* path) {
+  if (!d || !path) return lbm_fail(LBM_E_INVALID, "NULL argument");
+  FILE* f = fopen(path, "rb");
+  if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s", path);
+  CkptHeader h{};
+  const Layout L = layout_of(d->P);
+  const size_t pb = (size_t)d->ntiles * kPartials * sizeof(double);
+  if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "LBMCKPT1", 8) != 0 || h.nx != d->P.nx ||
+      h.ny != d->P.ny || h.storage != d->P.storage || h.isothermal != d->P.isothermal ||
+      h.state_bytes != L.state_bytes || h.fold_bytes != L.fold_bytes || h.part_bytes != pb) {
+    fclose(f);
+    return lbm_fail(LBM_E_INVALID, "%s does not match this domain (geometry, storage or tiling)", path);
+  }
+  std::vector<char> st(L.state_bytes), fo(L.fold_bytes), pa(pb);
+  double rb[2];
+  long long sd;
+  bool ok = fread(st.data(), 1, st.size(), f) == st.size() && fread(fo.data(), 1, fo.size(), f) == fo.size() &&
+            fread(pa.data(), 1, pa.size(), f) == pa.size() && fread(rb, sizeof(rb), 1, f) == 1 &&
+            fread(&sd, sizeof(sd), 1, f) == 1;
+  fclose(f);
+  if (!ok) return lbm_fail(LBM_E_INVALID, "%s is truncated", path);
+  d->step = h.step;
+  d->host.parity = 0;
+  HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
+  const int ph = (int)(d->step & 1);
+  HIPCHECK(hipMemcpy(d->host.buf[ph], st.data(), L.state_bytes, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(d->host.fold[ph], fo.data(), L.fold_bytes, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], pa.data(), pb, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(d->host.rbar, rb, sizeof(rb), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(d->host.step_dev, &sd, sizeof(sd), hipMemcpyHostToDevice));
+  d->inited = true;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ Maxwell construction
+extern "C" int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double* rho_v, double* p_sat) {
+  if (!p || !rho_l || !rho_v || !p_sat) return lbm_fail(LBM_E_INVALID, "NULL argument");
+  const double Tc = crit_T(*p);
+  if (!(T > 0 && T < Tc)) return lbm_fail(LBM_E_INVALID, "T must lie in (0, Tc = %g)", Tc);
+  const double b = p->b, a = p->a, R = p->R;
+  const double s = std::sqrt(T / Tc);
+  const double sa = 1.0 + kappa_of(*p) * (1.0 - s);
+  const double aa = a * sa * sa;
+  auto P = [&](double v) { return R * T / (v - b) - aa / (v * v + 2 * b * v - b * b); };
+  auto dP = [&](double v) {
+    const double q = v * v + 2 * b * v - b * b;
+    return -R * T / ((v - b) * (v - b)) + aa * (2 * v + 2 * b) / (q * q);
+  };
+  // primitive of P dv
+  const double r2 = std::sqrt(2.0);
+  auto I = [&](double v) {
+    return R * T * std::log(v - b) - aa / (2 * r2 * b) * std::log((v + b - r2 * b) / (v + b + r2 * b));
+  };
+  auto bisect = [](auto f, double lo, double hi) {
+    double flo = f(lo);
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      const double fm = f(mid);
+      if ((fm > 0) == (flo > 0)) {
+        lo = mid;
+        flo = fm;
+      } else {
+        hi = mid;
+      }
+    }
+    return 0.5 * (lo + hi);
+  };
+  // spinodals: sign changes of dP on a geometric grid of v
+  double vmin = 0, vmax = 0;
+  int found = 0;
+  double vprev = b * 1.0001, dprev = dP(vprev);
+  for (int k = 1; k <= 200000 && found < 2; ++k) {
+    const double v = b * 1.0001 * std::pow(1e4 / 1.0001, k / 200000.0);
+    const double dv = dP(v);
+    if ((dv > 0) != (dprev > 0)) {
+      const double root = bisect(dP, vprev, v);
+      if (found == 0) vmin = root; else vmax = root;
+      ++found;
+    }
+    vprev = v;
+    dprev = dv;
+  }
+  if (found < 2) return lbm_fail(LBM_E_INVALID, "no van der Waals loop at T = %g", T);
+  const double plo = std::max(P(vmin), 1e-9 * P(vmax)), phi = P(vmax);
+  auto roots = [&](double ps, double* vl, double* vg) {
+    *vl = bisect([&](double v) { return P(v) - ps; }, b * (1 + 1e-12), vmin);
+    double hi = 2 * vmax;
+    while (P(hi) >= ps) hi *= 2;
+    *vg = bisect([&](double v) { return P(v) - ps; }, vmax, hi);
+  };
+  auto area = [&](double ps) {
+    double vl, vg;
+    roots(ps, &vl, &vg);
+    return (I(vg) - I(vl)) - ps * (vg - vl);
+  };
+  const double eps = 1e-12 * (phi - plo);
+  const double ps = bisect(area, plo + eps, phi - eps);
+  double vl, vg;
+  roots(ps, &vl, &vg);
+  *rho_l = 1.0 / vl;
+  *rho_v = 1.0 / vg;
+  *p_sat = ps;
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_tile_rows(lbm_domain* d, int rows) {
+  if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  if (rows < 0) return lbm_fail(LBM_E_INVALID, "rows must be >= 0");
+  if (d->inited && d->step > 0) {
+    // the partial sums of the last launch are stored per tile: keep the mass
+    // total by re-finalizing into tile 0 of the new layout
+    const int ph = (int)(d->step & 1);
+    std::vector<double> old((size_t)d->ntiles * kPartials);
+    HIPCHECK(hipStreamSynchronize(d->stream));
+    HIPCHECK(hipMemcpy(old.data(), d->host.partials[ph ^ 1], old.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double tot[kPartials] = {0};
+    for (int t = 0; t < d->ntiles; ++t)
+      for (int q = 0; q < kPartials; ++q) tot[q] += old[(size_t)t * kPartials + q];
+    d->rows = rows == 0 ? kDefaultTileRows : std::max(rows, kMinTileRows);
+    int rc = lbm_build_tiles(d);
+    if (rc) return rc;
+    std::vector<double> nw((size_t)d->ntiles * kPartials, 0.0);
+    for (int q = 0; q < kPartials; ++q) nw[q] = tot[q];
+    HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice));
+    return LBM_OK;
+  }
+  d->rows = rows == 0 ? kDefaultTileRows : std::max(rows, kMinTileRows);
+  int rc = lbm_build_tiles(d);
+  if (rc) return rc;
+  if (d->inited) {
+    // re-seed the first-step partials for the new tile count
+    double rb[2];
+    HIPCHECK(hipMemcpy(rb, d->host.rbar, sizeof(rb), hipMemcpyDeviceToHost));
+    std::vector<double> parts((size_t)d->ntiles * kPartials, 0.0);
+    parts[P_MASS] = rb[1] * (double)d->P.nx * d->P.ny;
+    HIPCHECK(hipMemcpy(d->host.partials[1], parts.data(), parts.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src) return lbm_fail(LBM_E_INVALID, "NULL buffer");
+  if (((uintptr_t)dst & 15) || ((uintptr_t)src & 15) || (bytes & 15))
+    return lbm_fail(LBM_E_INVALID, "buffers and size must be 16-byte aligned");
+  HIPCHECK(lbm_launch_copy(dst, src, bytes, (hipStream_t)hip_stream));
+  return LBM_OK;
+}

@@ -1,0 +1,48 @@
+// Host-side objects behind the opaque handles of include/lbmflow.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/lbmflow.h"
+#include "lbm_internal.h"
+
+constexpr int kMinTileRows = 4;
+constexpr int kDefaultTileRows = 32;
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct lbm_domain {
+  lbm_params P{};
+  lbm::DevDomain host{};          // host copy of the device descriptor
+  lbm::DevDomain* dev = nullptr;  // device descriptor
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* mem = nullptr;
+  bool own_mem = false;
+  size_t bytes = 0;
+  std::vector<lbm::Tile> tiles_h;
+  lbm::Tile* tiles_d = nullptr;
+  int ntiles = 0;
+  int rows = kDefaultTileRows;
+  int grid = 0;  // 0: one workgroup per tile
+  float* psiw_d[2] = {nullptr, nullptr};
+  float* Tw_d[2] = {nullptr, nullptr};
+  int* heater_d = nullptr;
+  std::vector<int> heater_h;
+  std::vector<double> Tw_h[2];
+  int64_t step = 0;
+  bool inited = false;
+  bool in_batch = false;
+  std::vector<GraphEntry> graphs;  // [0]: two-step replay graph of this domain
+};
+
+int lbm_fail(int code, const char* fmt, ...);
+int lbm_build_tiles(lbm_domain* d);
+int lbm_enqueue_steps(lbm_domain* d, int64_t n);
+int lbm_run_steps(lbm_domain* d, int64_t n);
+void lbm_drop_graphs(lbm_domain* d);

@@ -1,0 +1,239 @@
+"""ctypes binding of liblbmflow.so (C ABI in include/lbmflow.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels of the library.  PyTorch, when used, supplies device memory
+(``data_ptr``) and streams; nothing here computes physics.  Loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbmflow.so")
+
+LBM_OK = 0
+STORE_F32, STORE_F32_DEV, STORE_F16_DEV, STORE_BF16_DEV = 0, 1, 2, 3
+BCX_PERIODIC, BCX_CHANNEL = 0, 1
+BCY_PERIODIC, BCY_WALLS = 0, 1
+SIDE_S, SIDE_N = 0, 1
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbmflow error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in (
+        "nx", "ny", "storage", "bc_x", "bc_y", "isothermal", "single_phase", "reserved")] + [
+        (n, C.c_double) for n in (
+            "a", "b", "R", "omega", "beta", "c0", "g", "tau_f", "s_e", "s_eps", "s_q",
+            "tau_g", "c_v", "ga_x", "ga_y", "fb_x", "fb_y", "u_in", "T_in", "U_out",
+            "T_iso", "rho_mid", "rho_ref", "T_ref")]
+
+
+class Diag(C.Structure):
+    _fields_ = [("step", C.c_int64)] + [(n, C.c_double) for n in (
+        "mass", "energy", "heater_q", "vapor_cells", "psi_clamped", "nonfinite", "p_in", "p_out")]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build the HIP library first (python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, fp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_float)
+        sig = {
+            "lbm_last_error": (C.c_char_p, []),
+            "lbm_params_default": (C.c_int, [C.POINTER(Params)]),
+            "lbm_required_bytes": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
+            "lbm_create": (C.c_int, [C.POINTER(Params), vp, vp, C.c_size_t, C.POINTER(vp)]),
+            "lbm_destroy": (C.c_int, [vp]),
+            "lbm_set_wall_maps": (C.c_int, [vp, C.c_int, dp, dp, C.POINTER(C.c_int32)]),
+            "lbm_init_fields": (C.c_int, [vp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_uint64]),
+            "lbm_step": (C.c_int, [vp, C.c_int64]),
+            "lbm_sync": (C.c_int, [vp]),
+            "lbm_step_count": (C.c_int64, [vp]),
+            "lbm_read_fields": (C.c_int, [vp, dp, dp, dp, dp]),
+            "lbm_read_fields_device": (C.c_int, [vp, vp, vp, vp, vp]),
+            "lbm_read_diag": (C.c_int, [vp, C.POINTER(Diag)]),
+            "lbm_diag_history": (C.c_int, [vp, C.POINTER(Diag), C.c_int, C.POINTER(C.c_int)]),
+            "lbm_save": (C.c_int, [vp, C.c_char_p]),
+            "lbm_load": (C.c_int, [vp, C.c_char_p]),
+            "lbm_maxwell": (C.c_int, [C.POINTER(Params), C.c_double, dp, dp, dp]),
+            "lbm_set_tile_rows": (C.c_int, [vp, C.c_int]),
+            "lbm_batch_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_char_p, C.POINTER(vp)]),
+            "lbm_batch_step": (C.c_int, [vp, C.c_int64]),
+            "lbm_batch_sync": (C.c_int, [vp]),
+            "lbm_batch_destroy": (C.c_int, [vp]),
+            "lbm_stream_copy": (C.c_int, [vp, vp, C.c_size_t, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != LBM_OK:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    _check(lib().lbm_params_default(C.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def required_bytes(p: Params) -> int:
+    n = C.c_size_t()
+    _check(lib().lbm_required_bytes(C.byref(p), C.byref(n)))
+    return n.value
+
+
+def maxwell(p: Params, T: float):
+    rl, rv, ps = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().lbm_maxwell(C.byref(p), float(T), C.byref(rl), C.byref(rv), C.byref(ps)))
+    return rl.value, rv.value, ps.value
+
+
+def stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int | None = None):
+    _check(lib().lbm_stream_copy(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), nbytes, C.c_void_p(stream or 0)))
+
+
+class Domain:
+    """One channel/box domain on the current HIP device."""
+
+    def __init__(self, params: Params, stream: int | None = None, device_buffer=None):
+        self.params = params
+        self.nx, self.ny = params.nx, params.ny
+        h = C.c_void_p()
+        ptr, nbytes = None, 0
+        self._buf = device_buffer  # keep the caller's tensor alive
+        if device_buffer is not None:
+            ptr = C.c_void_p(device_buffer.data_ptr())
+            nbytes = device_buffer.numel() * device_buffer.element_size()
+        _check(lib().lbm_create(C.byref(params), C.c_void_p(stream or 0), ptr, nbytes, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().lbm_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_wall(self, side: int, T_wall, rho_w, heater=None):
+        Tw = np.ascontiguousarray(np.broadcast_to(np.asarray(T_wall, float), (self.nx,)))
+        rw = np.ascontiguousarray(np.broadcast_to(np.asarray(rho_w, float), (self.nx,)))
+        hp = None
+        if heater is not None:
+            ha = np.ascontiguousarray(np.asarray(heater, dtype=np.int32))
+            hp = ha.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(lib().lbm_set_wall_maps(self.h, int(side), _dp(Tw), _dp(rw), hp))
+
+    def init(self, rho0=None, T0=None, rho_u=1.0, T_u=None, noise=0.0, seed=0):
+        T_u = self.params.T_in if T_u is None else T_u
+        shp = (self.ny, self.nx)
+        r = None if rho0 is None else np.ascontiguousarray(np.broadcast_to(np.asarray(rho0, float), shp))
+        t = None if T0 is None else np.ascontiguousarray(np.broadcast_to(np.asarray(T0, float), shp))
+        _check(lib().lbm_init_fields(self.h, None if r is None else _dp(r), None if t is None else _dp(t),
+                                     float(rho_u), float(T_u), float(noise), C.c_uint64(seed)))
+
+    def step(self, n: int = 1):
+        _check(lib().lbm_step(self.h, int(n)))
+
+    def sync(self):
+        _check(lib().lbm_sync(self.h))
+
+    @property
+    def steps(self) -> int:
+        return int(lib().lbm_step_count(self.h))
+
+    def fields(self) -> dict:
+        shp = (self.ny, self.nx)
+        out = {k: np.zeros(shp) for k in ("rho", "ux", "uy", "T")}
+        _check(lib().lbm_read_fields(self.h, *[_dp(out[k]) for k in ("rho", "ux", "uy", "T")]))
+        return out
+
+    def fields_device(self, rho, ux, uy, T):
+        """Write the fields into caller device buffers (e.g. torch float32 tensors)."""
+        ptrs = [C.c_void_p(t.data_ptr()) if t is not None else None for t in (rho, ux, uy, T)]
+        _check(lib().lbm_read_fields_device(self.h, *ptrs))
+
+    def diag(self) -> dict:
+        d = Diag()
+        _check(lib().lbm_read_diag(self.h, C.byref(d)))
+        return d.as_dict()
+
+    def diag_history(self, max_records: int = 4096) -> list:
+        arr = (Diag * max_records)()
+        n = C.c_int()
+        _check(lib().lbm_diag_history(self.h, arr, max_records, C.byref(n)))
+        return [arr[i].as_dict() for i in range(n.value)]
+
+    def save(self, path: str):
+        _check(lib().lbm_save(self.h, path.encode()))
+
+    def load(self, path: str):
+        _check(lib().lbm_load(self.h, path.encode()))
+
+    def set_tile_rows(self, rows: int):
+        _check(lib().lbm_set_tile_rows(self.h, int(rows)))
+
+
+class Batch:
+    """Several initialised domains stepped together, one launch per step."""
+
+    def __init__(self, domains, tune_cache: str | None = None):
+        self.domains = list(domains)
+        arr = (C.c_void_p * len(self.domains))(*[d.h.value for d in self.domains])
+        h = C.c_void_p()
+        _check(lib().lbm_batch_create(arr, len(self.domains),
+                                      None if tune_cache is None else tune_cache.encode(), C.byref(h)))
+        self.h = h
+
+    def step(self, n: int):
+        _check(lib().lbm_batch_step(self.h, int(n)))
+
+    def sync(self):
+        _check(lib().lbm_batch_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().lbm_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
