@@ -1,0 +1,221 @@
+"""Throughput of the coupled D2Q9 flow-boiling step on one MI355X.
+
+One "step" is one lattice time step of the whole path (pull + boundary
+rules, moments, EOS and pseudopotential, forces, source, MRT and thermal
+collisions, store, FP64 reductions) over the 1600x200 channel with FP32
+storage.  Inputs are resident in HBM before timing starts.  Prints one JSON
+line.  Extra measurements (HBM-resident 8192x1024 channel, FP16/BF16
+storage, the batched 64-channel ensemble, a device copy ceiling) ride along
+under "variants".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & HBM GB/s (coupled D2Q9+T step); batched MLUPS, p50/p99 solve time"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {0: 144, 1: 144, 2: 72, 3: 72}  # 18 values read + 18 written, once each
+KERNEL_SRC = os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def make_domain(L, W, cfg, storage, stream):
+    ref = dict(rho_ref=W.RHO_L, T_ref=cfg.T_sat) if storage != L.STORE_F32 else {}
+    p = L.default_params(storage=storage, **ref, **cfg.params())
+    d = L.Domain(p, stream=stream)
+    Ts, rws, heat, Tn, rwn = cfg.walls()
+    d.set_wall(L.SIDE_S, Ts, rws, heat)
+    d.set_wall(L.SIDE_N, Tn, rwn)
+    d.init(**cfg.init_args())
+    return d
+
+
+def time_domain(torch, d, steps, warmup):
+    """Wall time and HIP-event time (on the domain's stream) of `steps` steps."""
+    d.step(warmup)
+    d.sync()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    d.step(steps)
+    e1.record()
+    d.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, e0.elapsed_time(e1) / 1e3
+
+
+def cpu_baseline(W, budget_s=12.0):
+    """The FP64 oracle (OpenMP over rows) on the same 1600x200 channel: a
+    bounded sample of steps, timed with a steady clock around the steps only."""
+    from oracle import oracle as O
+
+    cfg = W.c2()
+    o = O.Oracle(O.Params(**cfg.params()))
+    Ts, rws, heat, Tn, rwn = cfg.walls()
+    o.set_wall(0, Ts, rws, heat)
+    o.set_wall(1, Tn, rwn)
+    o.init(**cfg.init_args())
+    o.step(2)
+    n, t = 0, 0.0
+    while t < budget_s:
+        t0 = time.perf_counter()
+        o.step(10)
+        t += time.perf_counter() - t0
+        n += 10
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    return {"value": round(cfg.nx * cfg.ny * n / t / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, channel {cfg.nx}x{cfg.ny}, {n} steps ({t:.1f} s), OpenMP threads={cores}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="only the headline workload")
+    ap.add_argument("--storage", default="F32_DEV", choices=["F32", "F32_DEV", "F16_DEV", "BF16_DEV"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
+              "the multi-GPU decomposition is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2009_05264_amd import lbmflow as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    # a non-default stream shared by torch and the library: events recorded by
+    # torch land on the stream the kernels are launched on
+    ts = torch.cuda.Stream()
+    torch.cuda.set_stream(ts)
+    stream = ts.cuda_stream
+    storage = getattr(L, "STORE_" + args.storage)
+
+    cfg = W.c2()
+    nodes = cfg.nx * cfg.ny
+    d = make_domain(L, W, cfg, storage, stream)
+    wall, ev = time_domain(torch, d, args.steps, args.warmup)
+    diag = d.diag()
+    d.close()
+    mlups = nodes * args.steps / wall / 1e6
+    launch_s = ev / args.steps
+    alg_bytes = BYTES_PER_LUP[storage] * nodes
+    achieved = alg_bytes / launch_s / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("kernel_sha") == kernel_sha() and t.get("workload") == f"{cfg.nx}x{cfg.ny}" \
+                and t.get("storage") == args.storage:
+            traffic = t.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if storage in (0, 1) else ("f32 compute, f16 storage" if storage == 2 else "f32 compute, bf16 storage"),
+        "data": "synthetic",
+        "config": {"workload": f"flow-boiling channel {cfg.nx}x{cfg.ny}, FP32 plain (single-instance) solver, "
+                               f"80-cell heater at 0.10 T_sat superheat, u_in=0.005",
+                   "nx": cfg.nx, "ny": cfg.ny, "storage": args.storage, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "step_kernel", "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": round(1e6 * launch_s, 3),
+                     "note": "1600x200 FP32 A/B state is 46 MB and fits the 256 MB Infinity Cache"},
+        "health": {"nonfinite": diag["nonfinite"], "psi_clamped": diag["psi_clamped"]},
+    }
+
+    if not args.no_variants:
+        var = {}
+        # HBM-resident channel (A/B state several times the Infinity Cache)
+        big = W.roofline_channel()
+        db = make_domain(L, W, big, L.STORE_F32_DEV, stream)
+        w2, e2 = time_domain(torch, db, 200, 20)
+        db.close()
+        bn = big.nx * big.ny
+        var["hbm_channel_8192x1024_f32"] = {
+            "MLUPS": round(bn * 200 / w2 / 1e6, 1),
+            "achieved_GBs": round(144 * bn / (e2 / 200) / 1e9, 1),
+            "frac_of_8TBs": round(144 * bn / (e2 / 200) / 1e9 / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(1e6 * e2 / 200, 2)}
+        # half-precision deviation storage at the headline size
+        for name, st in (("F16_DEV", L.STORE_F16_DEV), ("BF16_DEV", L.STORE_BF16_DEV)):
+            dh = make_domain(L, W, cfg, st, stream)
+            w3, e3 = time_domain(torch, dh, 2000, 200)
+            dh.close()
+            var[f"channel_1600x200_{name}"] = {"MLUPS": round(nodes * 2000 / w3 / 1e6, 1),
+                                               "achieved_GBs": round(72 * nodes / (e3 / 2000) / 1e9, 1)}
+            dh = make_domain(L, W, big, st, stream)
+            w3, e3 = time_domain(torch, dh, 200, 20)
+            dh.close()
+            var[f"hbm_channel_8192x1024_{name}"] = {
+                "MLUPS": round(bn * 200 / w3 / 1e6, 1),
+                "achieved_GBs": round(72 * bn / (e3 / 200) / 1e9, 1)}
+        # batched 64-channel ensemble vs the same channels one at a time
+        ens = W.ensemble()
+        doms = [make_domain(L, W, c, L.STORE_F32_DEV, stream) for c in ens]
+        tot = sum(c.nx * c.ny for c in ens)
+        nb = 400
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for dd in doms:
+            dd.step(nb)
+        torch.cuda.synchronize()
+        t_solo = time.perf_counter() - t0
+        b = L.Batch(doms, tune_cache="")  # autotune on the batch itself, no cache file
+        b.step(nb)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(nb)
+        b.sync()
+        t_batch = time.perf_counter() - t0
+        b.close()
+        for dd in doms:
+            dd.close()
+        var["ensemble_64_f32"] = {"nodes": tot, "steps": nb,
+                                  "batched_MLUPS": round(tot * nb / t_batch / 1e6, 1),
+                                  "one_at_a_time_MLUPS": round(tot * nb / t_solo / 1e6, 1)}
+        # device copy ceiling (read + write bytes / time)
+        n = 1 << 28
+        a = torch.empty(n // 4, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        L.stream_copy(c.data_ptr(), a.data_ptr(), n, stream)
+        torch.cuda.synchronize()  # (events below are on the same stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            L.stream_copy(c.data_ptr(), a.data_ptr(), n, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        var["copy_ceiling_GBs"] = round(2 * n * 20 / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+        del a, c
+        out["variants"] = var
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -58,7 +58,7 @@ static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int)
 
 static int enqueue_domain_phase(void* ctx, int phase) {
   lbm_domain* d = (lbm_domain*)ctx;
-  HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->grid, phase, d->stream));
+  HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->self_d, 1, d->grid, phase, d->stream));
   return LBM_OK;
 }
 
@@ -93,6 +93,8 @@ struct lbm_batch {
     Tile* tiles_d = nullptr;
     int ntiles = 0;
     int grid = 0;
+    DevDomain** doms_d = nullptr;  // domains whose reductions this launch finalizes
+    int ndoms = 0;
   };
   std::vector<Group> groups;
   GraphEntry graph;
@@ -103,20 +105,28 @@ struct lbm_batch {
 // Tiles of each domain in its own layout, concatenated in the order of the
 // domains, grouped by storage kind.
 static int build_groups(lbm_batch* b) {
-  for (auto& g : b->groups)
+  for (auto& g : b->groups) {
     if (g.tiles_d) (void)hipFree(g.tiles_d);
+    if (g.doms_d) (void)hipFree(g.doms_d);
+  }
   b->groups.clear();
   std::map<int, std::vector<Tile>> by;
+  std::map<int, std::vector<DevDomain*>> dby;
   for (lbm_domain* d : b->doms) {
     auto& v = by[d->P.storage];
     v.insert(v.end(), d->tiles_h.begin(), d->tiles_h.end());
+    dby[d->P.storage].push_back(d->dev);
   }
   for (auto& kv : by) {
     lbm_batch::Group g;
     g.storage = kv.first;
     g.ntiles = (int)kv.second.size();
+    const auto& dl = dby[kv.first];
+    g.ndoms = (int)dl.size();
     HIPCHECK(hipMalloc(&g.tiles_d, g.ntiles * sizeof(Tile)));
     HIPCHECK(hipMemcpy(g.tiles_d, kv.second.data(), g.ntiles * sizeof(Tile), hipMemcpyHostToDevice));
+    HIPCHECK(hipMalloc(&g.doms_d, g.ndoms * sizeof(DevDomain*)));
+    HIPCHECK(hipMemcpy(g.doms_d, dl.data(), g.ndoms * sizeof(DevDomain*), hipMemcpyHostToDevice));
     b->groups.push_back(g);
   }
   return LBM_OK;
@@ -125,7 +135,7 @@ static int build_groups(lbm_batch* b) {
 static int enqueue_batch_phase(void* ctx, int phase) {
   lbm_batch* b = (lbm_batch*)ctx;
   for (auto& g : b->groups)
-    HIPCHECK(lbm_launch_step(g.storage, g.tiles_d, g.ntiles, g.grid, phase, b->stream));
+    HIPCHECK(lbm_launch_step(g.storage, g.tiles_d, g.ntiles, g.doms_d, g.ndoms, g.grid, phase, b->stream));
   return LBM_OK;
 }
 
@@ -306,8 +316,10 @@ extern "C" int lbm_batch_destroy(lbm_batch* b) {
   if (!b) return LBM_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_batch_graph(b);
-  for (auto& g : b->groups)
+  for (auto& g : b->groups) {
     if (g.tiles_d) (void)hipFree(g.tiles_d);
+    if (g.doms_d) (void)hipFree(g.doms_d);
+  }
   for (lbm_domain* d : b->doms) {
     d->in_batch = false;
     d->host.parity = 0;

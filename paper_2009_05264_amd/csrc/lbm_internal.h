@@ -36,8 +36,9 @@ struct DevDomain {
   float ga_x, ga_y, fb_x, fb_y;
   float u_in, T_in, U_out, inv_1pU;  // inv_1pU = 1 / (1 + U_out)
   float in_geq;                      // T_in (1 + 3 u_in^2): inlet anti-bounce-back state
+  float inv_1mu;                     // 1 / (1 - u_in)
   float rho_ref, T_ref, T_iso, rho_mid;
-  float pad4[3];
+  float pad4[2];
   // buffers
   void* buf[2];         // state A/B: 9 f planes then 9 g planes (g absent when isothermal)
   float* fold[2];       // convective-outlet memory [3][ny] (deviation form), A/B
@@ -67,8 +68,8 @@ enum StepMode { MODE_STEP = 0, MODE_READOUT = 1 };
 }  // namespace lbm
 
 // Launch wrappers (lbm_kernels.hip).
-hipError_t lbm_launch_step(int storage, const lbm::Tile* tiles, int ntiles, int grid, int phase,
-                           hipStream_t s);
+hipError_t lbm_launch_step(int storage, const lbm::Tile* tiles, int ntiles,
+                           lbm::DevDomain* const* doms, int ndoms, int grid, int phase, hipStream_t s);
 hipError_t lbm_launch_readout(int storage, const lbm::Tile* tiles, int ntiles, int phase,
                               hipStream_t s);
 hipError_t lbm_launch_finalize(lbm::DevDomain* d, const double* partials, int ntiles, double* out8,

@@ -39,38 +39,105 @@ __device__ constexpr float WF[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
 
 // ---------------------------------------------------------------- storage
+// Distributions are addressed as (wave-uniform base, 32-bit per-lane byte
+// offset) in the global address space, which maps every load and store to
+// one saddr+voffset instruction.
+#define AS1 __attribute__((address_space(1)))
+#define AS4 __attribute__((address_space(4)))
+typedef const char AS1* gptr;
+typedef char AS1* gptr_w;
+
+__device__ __forceinline__ gptr_w as_global(const void* p) { return (gptr_w)(uintptr_t)p; }
+
 template <int S>
 struct Codec;
 template <>
 struct Codec<LBM_STORE_F32> {
-  using T = float;
-  static __device__ __forceinline__ float ld(const T* p, long long i) { return p[i]; }
-  static __device__ __forceinline__ void st(T* p, long long i, float v) { p[i] = v; }
+  static constexpr int E = 4;  // bytes per value
+  static __device__ __forceinline__ float ld(gptr b, uint32_t off) { return *(const float AS1*)(b + off); }
+  static __device__ __forceinline__ void st(gptr_w b, uint32_t off, float v) { *(float AS1*)(b + off) = v; }
 };
 template <>
 struct Codec<LBM_STORE_F32_DEV> : Codec<LBM_STORE_F32> {};
 template <>
 struct Codec<LBM_STORE_F16_DEV> {
-  using T = _Float16;
-  static __device__ __forceinline__ float ld(const T* p, long long i) { return (float)p[i]; }
-  static __device__ __forceinline__ void st(T* p, long long i, float v) {
+  static constexpr int E = 2;
+  static __device__ __forceinline__ float ld(gptr b, uint32_t off) {
+    return (float)*(const _Float16 AS1*)(b + off);
+  }
+  static __device__ __forceinline__ void st(gptr_w b, uint32_t off, float v) {
     v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
-    p[i] = (_Float16)v;
+    *(_Float16 AS1*)(b + off) = (_Float16)v;
   }
 };
 template <>
 struct Codec<LBM_STORE_BF16_DEV> {
-  using T = uint16_t;
-  static __device__ __forceinline__ float ld(const T* p, long long i) {
-    return __uint_as_float(((uint32_t)p[i]) << 16);
+  static constexpr int E = 2;
+  static __device__ __forceinline__ float ld(gptr b, uint32_t off) {
+    return __uint_as_float(((uint32_t) * (const uint16_t AS1*)(b + off)) << 16);
   }
-  static __device__ __forceinline__ void st(T* p, long long i, float v) {
+  static __device__ __forceinline__ void st(gptr_w b, uint32_t off, float v) {
     v = fminf(fmaxf(v, -3.3895313892515355e38f), 3.3895313892515355e38f);
     uint32_t u = __float_as_uint(v);
     u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    p[i] = (uint16_t)(u >> 16);
+    *(uint16_t AS1*)(b + off) = (uint16_t)(u >> 16);
   }
 };
+
+typedef const DevDomain AS4& DRef;
+
+// Raw buffer access for the interior path: one resource per buffer, a
+// wave-uniform byte offset per distribution plane (SGPR) and one per-lane
+// byte offset per row (VGPR).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7FFFFFFF, 0x00020000);
+}
+template <int S>
+struct BufIO;
+template <>
+struct BufIO<LBM_STORE_F32> {
+  template <int IMM>
+  static __device__ __forceinline__ float ld(Rsrc r, int voff, int soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * 4, soff, 0));
+  }
+  static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+  }
+};
+template <>
+struct BufIO<LBM_STORE_F32_DEV> : BufIO<LBM_STORE_F32> {};
+template <>
+struct BufIO<LBM_STORE_F16_DEV> {
+  template <int IMM>
+  static __device__ __forceinline__ float ld(Rsrc r, int voff, int soff) {
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, voff + IMM * 2, soff, 0);
+    return (float)__builtin_bit_cast(_Float16, u);
+  }
+  static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
+    v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, voff, soff, 0);
+  }
+};
+template <>
+struct BufIO<LBM_STORE_BF16_DEV> {
+  template <int IMM>
+  static __device__ __forceinline__ float ld(Rsrc r, int voff, int soff) {
+    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, voff + IMM * 2, soff, 0);
+    return __uint_as_float(((uint32_t)u) << 16);
+  }
+  static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
+    v = fminf(fmaxf(v, -3.3895313892515355e38f), 3.3895313892515355e38f);
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(u >> 16), r, voff, soff, 0);
+  }
+};
+
+// Hardware reciprocal and square root (1 ulp); the path needs no correctly
+// rounded division.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 __device__ __forceinline__ int wrap(int v, int n) {
   int r = v % n;
@@ -78,43 +145,92 @@ __device__ __forceinline__ int wrap(int v, int n) {
 }
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-// Per-lane data of one lattice row of the tile.
-struct Row {
-  float h[9], k[9];      // pulled distributions (deviation form)
-  float rho, drho, ux, uy, T, dT, inv_rho;
-  float psi, A, B, dpdT; // A = beta psi, B = psi^2 (wall rows: psi_w)
-  float Fx, Fy, uax, uay;
-};
-
 // Peng-Robinson EOS (Eq. 12), pseudopotential (Eq. 11), (dp/dT)_rho.
-__device__ __forceinline__ void eos(const DevDomain& D, float rho, float T, float& p, float& psi,
+__device__ __forceinline__ void eos(DRef D, float rho, float T, float& p, float& psi,
                                     float& dpdT, int& clamped) {
-  const float s = sqrtf(T * D.inv_Tc);
+  const float s = fsqrt(T * D.inv_Tc);
   const float sa = 1.f + D.kappa * (1.f - s);
   const float alpha = sa * sa;
   const float br = D.b * rho;
-  const float r1 = 1.f / (1.f - br);
-  const float r2 = 1.f / (1.f + br * (2.f - br));
+  const float r1 = rcp(1.f - br);
+  const float r2 = rcp(1.f + br * (2.f - br));
   const float ar2 = D.a * rho * rho * r2;
   p = rho * D.R * T * r1 - alpha * ar2;
   float q = (p - rho * (1.f / 3.f)) * D.c0g2;
   clamped = !(q >= 0.f);
   q = clamped ? 0.f : q;
-  psi = sqrtf(q);
-  dpdT = rho * D.R * r1 + ar2 * D.kappa * sa / (s * D.Tc);
+  psi = fsqrt(q);
+  dpdT = rho * D.R * r1 + ar2 * D.kappa * sa * rcp(s * D.Tc);
+}
+
+// Byte offset of distribution plane i (0-8 f, 9-17 g) at element idx.
+template <int S>
+__device__ __forceinline__ uint32_t boff(DRef D, int i, uint32_t idx) {
+  return (uint32_t)(i * (uint32_t)D.plane + idx) * (uint32_t)Codec<S>::E;
+}
+
+// Convective outlet for direction I (memory slot M) at node (nx-1, y): the
+// value pulled this step at (nx-2, y), i.e. the post-collision value of
+// direction I at (nx-1, y - cy_I), blended with the previous step's value.
+template <int S, int I, int M>
+__device__ __forceinline__ void outlet_dir(DRef D, gptr src, const float* fold, int y, bool thermal,
+                                           float h[9], float k[9]) {
+  using C = Codec<S>;
+  const int ny = D.ny;
+  const int ys = y - CY[I];
+  if (D.bc_y == LBM_BCY_WALLS && (ys < 0 || ys >= ny)) return;  // wall rule already applied
+  const int ysw = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+  const uint32_t sidx = (uint32_t)(ysw * D.pitch + (D.nx - 1));
+  const float hn = C::ld(src, boff<S>(D, I, sidx));
+  h[I] = (fold[M * ny + y] + D.U_out * hn) * D.inv_1pU;
+  if (thermal) k[I] = C::ld(src, boff<S>(D, 9 + I, sidx));
+}
+
+// Pull of an interior node (every source inside the domain).  The resource
+// base sits one row and one column before the buffer, so the source of
+// direction i is  plane offset (SGPR) + row offset of y - cy_i (one of three
+// VGPRs) + (1 - cx_i) elements (immediate).
+template <int S, int I>
+__device__ __forceinline__ float ld_dir(Rsrc rs, const int vrow[3], int soff) {
+  constexpr int m = 1 - CY[I];
+  constexpr int imm = 1 - CX[I];
+  return BufIO<S>::template ld<imm>(rs, vrow[m], soff);
+}
+
+template <int S>
+__device__ __forceinline__ void pull_fast(Rsrc rs, const int sp[18], const int vrow[3], bool thermal,
+                                          float h[9], float k[9]) {
+  h[0] = ld_dir<S, 0>(rs, vrow, sp[0]);
+  h[1] = ld_dir<S, 1>(rs, vrow, sp[1]);
+  h[2] = ld_dir<S, 2>(rs, vrow, sp[2]);
+  h[3] = ld_dir<S, 3>(rs, vrow, sp[3]);
+  h[4] = ld_dir<S, 4>(rs, vrow, sp[4]);
+  h[5] = ld_dir<S, 5>(rs, vrow, sp[5]);
+  h[6] = ld_dir<S, 6>(rs, vrow, sp[6]);
+  h[7] = ld_dir<S, 7>(rs, vrow, sp[7]);
+  h[8] = ld_dir<S, 8>(rs, vrow, sp[8]);
+  if (thermal) {
+    k[0] = ld_dir<S, 0>(rs, vrow, sp[9]);
+    k[1] = ld_dir<S, 1>(rs, vrow, sp[10]);
+    k[2] = ld_dir<S, 2>(rs, vrow, sp[11]);
+    k[3] = ld_dir<S, 3>(rs, vrow, sp[12]);
+    k[4] = ld_dir<S, 4>(rs, vrow, sp[13]);
+    k[5] = ld_dir<S, 5>(rs, vrow, sp[14]);
+    k[6] = ld_dir<S, 6>(rs, vrow, sp[15]);
+    k[7] = ld_dir<S, 7>(rs, vrow, sp[16]);
+    k[8] = ld_dir<S, 8>(rs, vrow, sp[17]);
+  }
 }
 
 // Pull of node (xc, y) from the post-collision buffer with the boundary
 // rules (bounce-back / anti-bounce-back at wall rows, Zou-He inlet,
 // convective outlet).  xc in [0, nx), y in [0, ny).
 template <int S>
-__device__ __forceinline__ void pull(const DevDomain& D, const typename Codec<S>::T* src,
-                                     const float* fold, int xc, int y, bool thermal, float h[9],
-                                     float k[9]) {
+__device__ __forceinline__ void pull(DRef D, gptr src, const float* fold, int xc, int y,
+                                     bool thermal, float h[9], float k[9]) {
   using C = Codec<S>;
   const int nx = D.nx, ny = D.ny;
-  const long long pl = D.plane;
-  const long long own = (long long)y * D.pitch + xc;
+  const uint32_t own = (uint32_t)(y * D.pitch + xc);
   const bool walls = D.bc_y == LBM_BCY_WALLS;
   const bool chan = D.bc_x == LBM_BCX_CHANNEL;
 #pragma unroll
@@ -124,18 +240,18 @@ __device__ __forceinline__ void pull(const DevDomain& D, const typename Codec<S>
     if (walls && (ys < 0 || ys >= ny)) {
       const int o = OPP[i];
       const int xm = chan ? clampi(xs, 0, nx - 1) : (xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs));
-      h[i] = C::ld(src, o * pl + own);
+      h[i] = C::ld(src, boff<S>(D, o, own));
       if (thermal) {
         const float Tw = (ys < 0 ? D.Tw[0] : D.Tw[1])[xm];
-        k[i] = -C::ld(src, (9 + o) * pl + own) + 2.f * WF[i] * (Tw - D.T_ref);
+        k[i] = -C::ld(src, boff<S>(D, 9 + o, own)) + 2.f * WF[i] * (Tw - D.T_ref);
       }
     } else {
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
       if (!chan) xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
       if (xs >= 0 && xs < nx) {
-        const long long idx = (long long)ys * D.pitch + xs;
-        h[i] = C::ld(src, i * pl + idx);
-        if (thermal) k[i] = C::ld(src, (9 + i) * pl + idx);
+        const uint32_t idx = (uint32_t)(ys * D.pitch + xs);
+        h[i] = C::ld(src, boff<S>(D, i, idx));
+        if (thermal) k[i] = C::ld(src, boff<S>(D, 9 + i, idx));
       } else {
         h[i] = 0.f;  // ghost source: set by the inlet / outlet rule below
         k[i] = 0.f;
@@ -146,7 +262,7 @@ __device__ __forceinline__ void pull(const DevDomain& D, const typename Codec<S>
   if (xc == 0) {
     // Zou-He velocity inlet; unknowns are 1, 5, 8 unless a wall row is the source.
     const float u = D.u_in;
-    const float rin = (D.rho_ref + h[0] + h[2] + h[4] + 2.f * (h[3] + h[6] + h[7])) / (1.f - u);
+    const float rin = (D.rho_ref + h[0] + h[2] + h[4] + 2.f * (h[3] + h[6] + h[7])) * D.inv_1mu;
     const bool unk5 = !(walls && y - 1 < 0);
     const bool unk8 = !(walls && y + 1 >= ny);
     const float d24 = 0.5f * (h[2] - h[4]);
@@ -155,80 +271,46 @@ __device__ __forceinline__ void pull(const DevDomain& D, const typename Codec<S>
     if (unk8) h[8] = h[6] + d24 + rin * u * (1.f / 6.f);
     if (thermal) {
       const float gin = D.in_geq - D.T_ref;
-      k[1] = -C::ld(src, (9 + 3) * pl + own) + 2.f * WF[1] * gin;
-      if (unk5) k[5] = -C::ld(src, (9 + 7) * pl + own) + 2.f * WF[5] * gin;
-      if (unk8) k[8] = -C::ld(src, (9 + 6) * pl + own) + 2.f * WF[8] * gin;
+      k[1] = -C::ld(src, boff<S>(D, 9 + 3, own)) + 2.f * WF[1] * gin;
+      if (unk5) k[5] = -C::ld(src, boff<S>(D, 9 + 7, own)) + 2.f * WF[5] * gin;
+      if (unk8) k[8] = -C::ld(src, boff<S>(D, 9 + 6, own)) + 2.f * WF[8] * gin;
     }
   }
   if (xc == nx - 1) {
     // Convective outlet for 3, 6, 7 from the values just pulled at nx-2.
-    const int xn = nx - 2;
-    const long long own2 = (long long)y * D.pitch + xn;
-    const int dirs[3] = {3, 6, 7};
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const int i = dirs[m];
-      const int ys = y - CY[i];
-      if (walls && (ys < 0 || ys >= ny)) continue;  // wall rule already applied
-      const int ysw = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-      // pull of direction i at (nx-2, y): source (nx-1, y - cy)
-      const long long sidx = (long long)ysw * D.pitch + (nx - 1);
-      float hn, kn = 0.f;
-      hn = C::ld(src, i * pl + sidx);
-      if (thermal) kn = C::ld(src, (9 + i) * pl + sidx);
-      (void)own2;
-      h[i] = (fold[m * ny + y] + D.U_out * hn) * D.inv_1pU;
-      if (thermal) k[i] = kn;
-    }
-  }
-}
-
-template <int S>
-__device__ __forceinline__ void store_node(const DevDomain& D, typename Codec<S>::T* dst, int x,
-                                           int y, bool thermal, const float hs[9],
-                                           const float ks[9]) {
-  using C = Codec<S>;
-  const long long idx = (long long)y * D.pitch + x;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) C::st(dst, i * D.plane + idx, hs[i]);
-  if (thermal) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) C::st(dst, (9 + i) * D.plane + idx, ks[i]);
+    outlet_dir<S, 3, 0>(D, src, fold, y, thermal, h, k);
+    outlet_dir<S, 6, 1>(D, src, fold, y, thermal, h, k);
+    outlet_dir<S, 7, 2>(D, src, fold, y, thermal, h, k);
   }
 }
 
 // MRT collision with exact-difference forcing, in deviation form.  b_k =
 // S_k m_k(f - f^eq) - m_k(Delta F) for the moments (rho, e, eps, jx, qx, jy,
 // qy, pxx, pxy) of the Lallemand-Luo basis, f* = f - M^-1 b.
-__device__ __forceinline__ void collide_f(const DevDomain& D, const Row& R, float hs[9]) {
-  const float* h = R.h;
+__device__ __forceinline__ void collide_f(DRef D, const float h[9], float drho, float jx,
+                                          float jy, float ux, float uy, float Fx, float Fy,
+                                          float irho, float hs[9]) {
   const float A13 = h[1] + h[3], A24 = h[2] + h[4];
   const float Dg = h[5] + h[6] + h[7] + h[8];
   const float d13 = h[1] - h[3], d24 = h[2] - h[4];
   const float d57 = h[5] - h[7], d86 = h[8] - h[6];
-  const float jx = d13 + d57 + d86;
-  const float jy = d24 + d57 - d86;
   const float me = -4.f * h[0] - (A13 + A24) + 2.f * Dg;
   const float meps = 4.f * h[0] - 2.f * (A13 + A24) + Dg;
   const float mqx = -2.f * d13 + d57 + d86;
   const float mqy = -2.f * d24 + d57 - d86;
   const float mxx = A13 - A24;
   const float mxy = (h[5] + h[7]) - (h[6] + h[8]);
-  const float ux = R.ux, uy = R.uy;
-  const float rho = R.rho;
   const float ru2 = jx * ux + jy * uy;  // rho u^2
   // non-equilibrium parts
-  const float ne = me + 2.f * R.drho - 3.f * ru2;
-  const float neps = meps - R.drho + 3.f * ru2;
+  const float ne = me + 2.f * drho - 3.f * ru2;
+  const float neps = meps - drho + 3.f * ru2;
   const float nqx = mqx + jx;
   const float nqy = mqy + jy;
   const float nxx = mxx - (jx * ux - jy * uy);
   const float nxy = mxy - jx * uy;
   // forcing: Delta u = F/rho, s = 2u + Delta u
-  const float Fx = R.Fx, Fy = R.Fy;
-  const float sx = 2.f * ux + Fx * R.inv_rho, sy = 2.f * uy + Fy * R.inv_rho;
+  const float sx = 2.f * ux + Fx * irho, sy = 2.f * uy + Fy * irho;
   const float Fs = Fx * sx + Fy * sy;
-  (void)rho;
   const float ae = (D.s_e * ne - 3.f * Fs) * (1.f / 36.f);
   const float aeps = (D.s_eps * neps + 3.f * Fs) * (1.f / 36.f);
   const float aqx = (D.s_q * nqx + Fx) * (1.f / 12.f);
@@ -251,16 +333,17 @@ __device__ __forceinline__ void collide_f(const DevDomain& D, const Row& R, floa
 }
 
 // BGK relaxation of g towards g^eq(T, u_act) plus the source w_i phi.
-__device__ __forceinline__ void collide_g(const DevDomain& D, const Row& R, float phi, float ks[9]) {
+__device__ __forceinline__ void collide_g(DRef D, const float k[9], float dT, float T,
+                                          float uax, float uay, float phi, float ks[9]) {
   const float om = D.omega_g;
-  const float tT = om * R.T;
-  const float u2 = R.uax * R.uax + R.uay * R.uay;
-  const float base = om * R.dT + phi - 1.5f * tT * u2;
+  const float tT = om * T;
+  const float u2 = uax * uax + uay * uay;
+  const float base = om * dT + phi - 1.5f * tT * u2;
   const float keep = 1.f - om;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const float cu = (float)CX[i] * R.uax + (float)CY[i] * R.uay;
-    ks[i] = keep * R.k[i] + WF[i] * (base + tT * cu * (3.f + 4.5f * cu));
+    const float cu = (float)CX[i] * uax + (float)CY[i] * uay;
+    ks[i] = keep * k[i] + WF[i] * (base + tT * cu * (3.f + 4.5f * cu));
   }
 }
 
@@ -283,91 +366,118 @@ __device__ __forceinline__ void sum_partials(const double* parts, int ntiles, do
   for (int q = 0; q < kPartials; ++q) out[q] = wave_sum(out[q]);
 }
 
+// Per-lane data of the row whose force is being formed (stage 2) and of the
+// row below it (stage 3).
+struct RowA {  // row r: just pulled
+  float h[9], k[9];
+  float drho, jx, jy, dT, psi, A, B, dpdT;
+};
+
 template <int S, int MODE>
-__device__ void run_tile(const Tile& tl, int gphase) {
+__device__ void run_tile(const Tile AS4& tl, int gphase) {
   using C = Codec<S>;
-  const DevDomain& D = *tl.d;
+  DRef D = *(const DevDomain AS4*)tl.d;
   const int lane = threadIdx.x & (kWave - 1);
   const int phase = gphase ^ D.parity;
   const int nx = D.nx, ny = D.ny;
   const bool chan = D.bc_x == LBM_BCX_CHANNEL;
   const bool walls = D.bc_y == LBM_BCY_WALLS;
   const bool thermal = !D.isothermal;
-  const typename C::T* src = (const typename C::T*)D.buf[phase];
-  typename C::T* dst = (typename C::T*)D.buf[phase ^ 1];
+  gptr src = as_global(D.buf[phase]);
+  gptr_w dst = as_global(D.buf[phase ^ 1]);
   const float* fold = D.fold[phase];
   float* fold_dst = D.fold[phase ^ 1];
 
-  if (MODE == MODE_STEP && tl.local == 0) {
-    // Finalize the previous launch's reductions of this domain.
-    double sums[kPartials];
-    sum_partials(D.partials[phase ^ 1], D.ntiles, sums);
-    if (lane == 0) {
-      const long long st = *D.step_dev;
-      D.rbar[phase ^ 1] = sums[P_MASS] / ((double)nx * (double)ny);
-      DiagRec& rec = D.ring[(st + kRing) % kRing];
-      rec.step = st - 1;
-#pragma unroll
-      for (int q = 0; q < kPartials; ++q) rec.v[q] = sums[q];
-      *D.step_dev = st + 1;
-    }
-  }
-
   const int x = tl.x0 - 2 + lane;
   const int xc = chan ? clampi(x, 0, nx - 1) : wrap(x, nx);
-  const int xw = xc;  // wall-map column of this lane's solid cells
   const bool interior = lane >= 2 && lane < kWave - 2 && x < nx;
   const float gbar = (float)((double)D.rho_ref - D.rbar[phase]);  // rho_ref - rho_bar
+  const bool xlo = chan && x == 0, xhi = chan && x == nx - 1;
 
   double acc_mass = 0.0, acc_energy = 0.0, acc_q = 0.0;
   int acc_vap = 0, acc_clamp = 0, acc_nf = 0;
   double acc_pin = 0.0, acc_pout = 0.0;
 
-  Row R0, R1, R2;
-  bool s0 = false, s1 = false, s2 = false;  // solid flags of the three slots
-  float uy_prev = 0.f;                      // u_act,y of the row below the collided one
-  bool sprev = false;
+  // row r (a), row r-1 (b), row r-2 (c); s* = wall row flags
+  RowA a;
+  bool sa = false;
+  float bh[9], bk[9];
+  float b_drho = 0.f, b_jx = 0.f, b_jy = 0.f, b_dT = 0.f, b_psi = 0.f, b_A = 0.f, b_B = 0.f, b_dpdT = 0.f;
+  bool sb = false;
+  float ck[9];
+  float c_A = 0.f, c_B = 0.f, c_dT = 0.f, c_dpdT = 0.f, c_irho = 0.f, c_uax = 0.f, c_uay = 0.f;
+  bool sc = false;
+  float d_uay = 0.f;  // u_act,y of row r-3
+  bool sd = false;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) bh[i] = bk[i] = ck[i] = 0.f;
 
   const int r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
+  // The pull of row r + 1 is issued before row r is processed, so its memory
+  // latency overlaps the arithmetic of the current iteration.
+  float nh[9], nk[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nh[i] = nk[i] = 0.f;
+  // A tile whose 64 columns and their x-neighbours lie inside the domain
+  // pulls interior rows with no boundary logic, through buffer resources.
+  const bool xfast = tl.x0 >= 3 && tl.x0 + kWave - 2 < nx;
+  constexpr int E = C::E;
+  const int pitch = D.pitch;
+  const int plane = (int)D.plane;
+  const Rsrc rs = make_rsrc((const char*)D.buf[phase] - (pitch + 1) * E);
+  const Rsrc rd = make_rsrc(D.buf[phase ^ 1]);
+  int sst[18];  // byte offset of each distribution plane
+#pragma unroll
+  for (int i = 0; i < 18; ++i) sst[i] = i * plane * E;
+  auto fetch = [&](int rr) {
+    if (xfast && rr >= 1 && rr <= ny - 2) {
+      const int v0 = (rr * pitch + xc) * E;
+      const int vrow[3] = {v0, v0 + pitch * E, v0 + 2 * pitch * E};
+      pull_fast<S>(rs, sst, vrow, thermal, nh, nk);
+    }
+    else if (!(walls && (rr < 0 || rr >= ny))) {
+      pull<S>(D, src, fold, xc, walls ? rr : wrap(rr, ny), thermal, nh, nk);
+    }
+  };
+  fetch(tl.y0 - 2);
   for (int r = tl.y0 - 2; r <= r_end; ++r) {
-    // ---- stage 1: row r into R0
-    const bool solid = walls && (r < 0 || r >= ny);
-    if (solid) {
-      const float pw = (r < 0 ? D.psiw[0] : D.psiw[1])[xw];
-      R0.psi = pw;
-      R0.A = D.beta * pw;
-      R0.B = pw * pw;
+    // ---------------- stage 1: row r
+    sa = walls && (r < 0 || r >= ny);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      a.h[i] = nh[i];
+      a.k[i] = nk[i];
+    }
+    if (r < r_end) fetch(r + 1);
+    if (sa) {
+      const float pw = (r < 0 ? D.psiw[0] : D.psiw[1])[xc];
+      a.psi = pw;
+      a.A = D.beta * pw;
+      a.B = pw * pw;
     } else {
       const int ry = walls ? r : wrap(r, ny);
-      pull<S>(D, src, fold, xc, ry, thermal, R0.h, R0.k);
       float drho = 0.f, dT = 0.f;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) drho += R0.h[i];
+      for (int i = 0; i < 9; ++i) drho += a.h[i];
       if (thermal) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) dT += R0.k[i];
+        for (int i = 0; i < 9; ++i) dT += a.k[i];
       } else {
         dT = D.T_iso - D.T_ref;
       }
       const float rho = D.rho_ref + drho;
       const float T = D.T_ref + dT;
-      const float jx = (R0.h[1] - R0.h[3]) + (R0.h[5] - R0.h[7]) + (R0.h[8] - R0.h[6]);
-      const float jy = (R0.h[2] - R0.h[4]) + (R0.h[5] - R0.h[7]) + (R0.h[6] - R0.h[8]);
-      const float inv_rho = 1.f / rho;
-      R0.rho = rho;
-      R0.drho = drho;
-      R0.T = T;
-      R0.dT = dT;
-      R0.inv_rho = inv_rho;
-      R0.ux = jx * inv_rho;
-      R0.uy = jy * inv_rho;
+      a.drho = drho;
+      a.dT = dT;
+      a.jx = (a.h[1] - a.h[3]) + (a.h[5] - a.h[7]) + (a.h[8] - a.h[6]);
+      a.jy = (a.h[2] - a.h[4]) + (a.h[5] - a.h[7]) + (a.h[6] - a.h[8]);
       float p, psi, dpdT;
       int clamped;
       eos(D, rho, T, p, psi, dpdT, clamped);
-      R0.psi = psi;
-      R0.A = D.beta * psi;
-      R0.B = psi * psi;
-      R0.dpdT = dpdT;
+      a.psi = psi;
+      a.A = D.beta * psi;
+      a.B = psi * psi;
+      a.dpdT = dpdT;
       if (interior && r >= tl.y0 && r < tl.y1) {
         acc_mass += (double)rho;
         acc_energy += (double)T;
@@ -380,85 +490,109 @@ __device__ void run_tile(const Tile& tl, int gphase) {
           if (x == nx - 1) acc_pout = (double)p;
         }
         if (MODE == MODE_STEP && chan && x == nx - 1) {
-          fold_dst[0 * ny + ry] = R0.h[3];
-          fold_dst[1 * ny + ry] = R0.h[6];
-          fold_dst[2 * ny + ry] = R0.h[7];
-        }
-      }
-    }
-    s0 = solid;
-
-    // ---- stage 2: force and actual velocity of row q = r - 1 (slot R1)
-    if (r >= tl.y0) {
-      if (s1) {
-        R1.uax = 0.f;
-        R1.uay = 0.f;
-      } else {
-        float Fx = 0.f, Fy = 0.f;
-        if (!D.single_phase) {
-          const float VA = D.G1 * R1.A + D.G2 * (R0.A + R2.A);
-          const float VB = D.G1 * R1.B + D.G2 * (R0.B + R2.B);
-          const float DA = R0.A - R2.A;
-          const float DB = R0.B - R2.B;
-          const float VAr = __shfl_down(VA, 1, kWave), VAl = __shfl_up(VA, 1, kWave);
-          const float VBr = __shfl_down(VB, 1, kWave), VBl = __shfl_up(VB, 1, kWave);
-          const float DAr = __shfl_down(DA, 1, kWave), DAl = __shfl_up(DA, 1, kWave);
-          const float DBr = __shfl_down(DB, 1, kWave), DBl = __shfl_up(DB, 1, kWave);
-          const float SAx = VAr - VAl, SBx = VBr - VBl;
-          const float SAy = D.G1 * DA + D.G2 * (DAr + DAl);
-          const float SBy = D.G1 * DB + D.G2 * (DBr + DBl);
-          Fx = -R1.psi * SAx - D.half_1mb * SBx;
-          Fy = -R1.psi * SAy - D.half_1mb * SBy;
-        }
-        const float dr = R1.drho + gbar;  // rho - rho_bar
-        Fx += dr * D.ga_x + D.fb_x;
-        Fy += dr * D.ga_y + D.fb_y;
-        R1.Fx = Fx;
-        R1.Fy = Fy;
-        R1.uax = R1.ux + 0.5f * Fx * R1.inv_rho;
-        R1.uay = R1.uy + 0.5f * Fy * R1.inv_rho;
-        if (MODE == MODE_READOUT && interior && r - 1 >= tl.y0 && r - 1 < tl.y1) {
-          const long long o = (long long)(r - 1) * nx + x;
-          D.out[0][o] = R1.rho;
-          D.out[1][o] = R1.uax;
-          D.out[2][o] = R1.uay;
-          D.out[3][o] = R1.T;
+          fold_dst[0 * ny + ry] = a.h[3];
+          fold_dst[1 * ny + ry] = a.h[6];
+          fold_dst[2 * ny + ry] = a.h[7];
         }
       }
     }
 
-    // ---- stage 3: source and collisions of row c = r - 2 (slot R2)
-    if (MODE == MODE_STEP && r >= tl.y0 + 2) {
-      const int c = r - 2;
-      float uxl = __shfl_up(R2.uax, 1, kWave);
-      float uxr = __shfl_down(R2.uax, 1, kWave);
-      if (chan) {
-        if (x == 0) uxl = R2.uax;
-        if (x == nx - 1) uxr = R2.uax;
+    // ---------------- stage 2: row q = r - 1 (b): force, u_act, f collision
+    float b_uax = 0.f, b_uay = 0.f, b_irho = 0.f;
+    if (r >= tl.y0 && !sb) {
+      float Fx = 0.f, Fy = 0.f;
+      if (!D.single_phase) {
+        const float VA = D.G1 * b_A + D.G2 * (a.A + c_A);
+        const float VB = D.G1 * b_B + D.G2 * (a.B + c_B);
+        const float DA = a.A - c_A;
+        const float DB = a.B - c_B;
+        const float VAr = __shfl_down(VA, 1, kWave), VAl = __shfl_up(VA, 1, kWave);
+        const float VBr = __shfl_down(VB, 1, kWave), VBl = __shfl_up(VB, 1, kWave);
+        const float DAr = __shfl_down(DA, 1, kWave), DAl = __shfl_up(DA, 1, kWave);
+        const float DBr = __shfl_down(DB, 1, kWave), DBl = __shfl_up(DB, 1, kWave);
+        const float SAx = VAr - VAl, SBx = VBr - VBl;
+        const float SAy = D.G1 * DA + D.G2 * (DAr + DAl);
+        const float SBy = D.G1 * DB + D.G2 * (DBr + DBl);
+        Fx = -b_psi * SAx - D.half_1mb * SBx;
+        Fy = -b_psi * SAy - D.half_1mb * SBy;
       }
+      const float dr = b_drho + gbar;  // rho - rho_bar
+      Fx += dr * D.ga_x + D.fb_x;
+      Fy += dr * D.ga_y + D.fb_y;
+      const float rho = D.rho_ref + b_drho;
+      b_irho = rcp(rho);
+      const float ux = b_jx * b_irho, uy = b_jy * b_irho;
+      b_uax = ux + 0.5f * Fx * b_irho;
+      b_uay = uy + 0.5f * Fy * b_irho;
+      const int q = r - 1;
+      if (MODE == MODE_READOUT) {
+        if (interior && q >= tl.y0 && q < tl.y1) {
+          const long long o = (long long)q * nx + x;
+          D.out[0][o] = rho;
+          D.out[1][o] = b_uax;
+          D.out[2][o] = b_uay;
+          D.out[3][o] = D.T_ref + b_dT;
+        }
+      } else if (q >= tl.y0 && q < tl.y1) {
+        float hs[9];
+        collide_f(D, bh, b_drho, b_jx, b_jy, ux, uy, Fx, Fy, b_irho, hs);
+        if (interior) {
+          const int voff = (q * pitch + x) * E;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[i], hs[i]);
+        }
+      }
+    }
+
+    // ---------------- stage 3: row c = r - 2: source and g collision
+    if (MODE == MODE_STEP && thermal && r >= tl.y0 + 2) {
+      const int cr = r - 2;
+      float uxl = __shfl_up(c_uax, 1, kWave);
+      float uxr = __shfl_down(c_uax, 1, kWave);
+      if (xlo) uxl = c_uax;
+      if (xhi) uxr = c_uax;
       const float dux = 0.5f * (uxr - uxl);
-      const float un_c = s1 ? R2.uay : R1.uay, un_m = s1 ? -R2.uay : R1.uay;
-      const float us_c = sprev ? R2.uay : uy_prev, us_m = sprev ? -R2.uay : uy_prev;
+      const float un_c = sb ? c_uay : b_uay, un_m = sb ? -c_uay : b_uay;
+      const float us_c = sd ? c_uay : d_uay, us_m = sd ? -c_uay : d_uay;
       const float div_adv = dux + 0.5f * (un_c - us_c);
       const float div_mass = dux + 0.5f * (un_m - us_m);
-      const float phi = R2.T * (div_adv - R2.dpdT * R2.inv_rho * D.inv_cv * div_mass);
-      float hs[9], ks[9];
-      collide_f(D, R2, hs);
-      if (thermal) collide_g(D, R2, phi, ks);
-      if (interior) store_node<S>(D, dst, x, walls ? c : wrap(c, ny), thermal, hs, ks);
-      uy_prev = R2.uay;
-      sprev = s2;
-    } else if (MODE == MODE_STEP && r == tl.y0 + 1) {
-      // row y0 - 1 becomes the "row below" of the first collided row
-      uy_prev = R2.uay;
-      sprev = s2;
+      const float T = D.T_ref + c_dT;
+      const float phi = T * (div_adv - c_dpdT * c_irho * D.inv_cv * div_mass);
+      float ks[9];
+      collide_g(D, ck, c_dT, T, c_uax, c_uay, phi, ks);
+      if (interior) {
+        const int voff = (cr * pitch + x) * E;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[9 + i], ks[i]);
+      }
     }
 
-    // rotate slots: R2 <- R1 <- R0
-    R2 = R1;
-    R1 = R0;
-    s2 = s1;
-    s1 = s0;
+    // ---------------- rotate: d <- c <- b <- a
+    d_uay = c_uay;
+    sd = sc;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      ck[i] = bk[i];
+      bk[i] = a.k[i];
+      bh[i] = a.h[i];
+    }
+    c_A = b_A;
+    c_B = b_B;
+    c_dT = b_dT;
+    c_dpdT = b_dpdT;
+    c_irho = b_irho;
+    c_uax = b_uax;
+    c_uay = b_uay;
+    sc = sb;
+    b_drho = a.drho;
+    b_jx = a.jx;
+    b_jy = a.jy;
+    b_dT = a.dT;
+    b_psi = a.psi;
+    b_A = a.A;
+    b_B = a.B;
+    b_dpdT = a.dpdT;
+    sb = sa;
   }
 
   // ---- tile partial sums (fixed order: lane tree)
@@ -483,13 +617,42 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return k * q + min(k, rem) + i;
 }
 
+// Sum of the previous launch's per-tile partials of one domain: lagged mean
+// density for the buoyancy force, the diagnostics record, the step counter.
+__device__ void finalize_domain(DRef D, int gphase) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int phase = gphase ^ D.parity;
+  double sums[kPartials];
+  sum_partials(D.partials[phase ^ 1], D.ntiles, sums);
+  if (lane == 0) {
+    const long long st = *D.step_dev;
+    D.rbar[phase ^ 1] = sums[P_MASS] / ((double)D.nx * (double)D.ny);
+    DiagRec& rec = D.ring[(st + kRing) % kRing];
+    rec.step = st - 1;
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) rec.v[q] = sums[q];
+    *D.step_dev = st + 1;
+  }
+}
+
+// Blocks [0, kFinalizers) finalize the domains' reductions while the other
+// blocks process tiles; tile blocks keep the XCD of their index (kFinalizers
+// is a multiple of the 8 XCDs).
+constexpr int kFinalizers = 8;
+
 template <int S, int MODE>
-__global__ __launch_bounds__(kWave) void step_kernel(const Tile* __restrict__ tiles, int ntiles,
-                                                     int gphase) {
-  for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void step_kernel(
+    const Tile* __restrict__ tiles, int ntiles, DevDomain* const* __restrict__ doms, int ndoms,
+    int gphase) {
+  if (MODE == MODE_STEP && blockIdx.x < kFinalizers) {
+    for (int i = blockIdx.x; i < ndoms; i += kFinalizers)
+      finalize_domain(*(const DevDomain AS4*)((DevDomain* const AS4*)doms)[i], gphase);
+    return;
+  }
+  const int nb = gridDim.x - (MODE == MODE_STEP ? kFinalizers : 0);
+  for (int b = blockIdx.x - (MODE == MODE_STEP ? kFinalizers : 0); b < ntiles; b += nb) {
     const int t = xcd_tile(b, ntiles);
-    const Tile tl = tiles[t];
-    run_tile<S, MODE>(tl, gphase);
+    run_tile<S, MODE>(((const Tile AS4*)tiles)[t], gphase);
   }
 }
 
@@ -514,6 +677,7 @@ __global__ void init_kernel(DevDomain D, const double* rho0, const double* T0, d
                             double T_u, double noise, unsigned long long seed, int b) {
   using C = Codec<S>;
   const long long n = (long long)D.nx * D.ny;
+  gptr_w buf = as_global(D.buf[b]);
   for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
        id += (long long)gridDim.x * blockDim.x) {
     const int x = (int)(id % D.nx), y = (int)(id / D.nx);
@@ -526,14 +690,15 @@ __global__ void init_kernel(DevDomain D, const double* rho0, const double* T0, d
       r = rho_u * (1.0 + noise * (2.0 * u - 1.0));
     }
     const double t = T0 ? T0[id] : T_u;
-    typename C::T* buf = (typename C::T*)D.buf[b];
-    const long long idx = (long long)y * D.pitch + x;
+    const uint32_t idx = (uint32_t)(y * D.pitch + x);
     const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    for (int i = 0; i < 9; ++i) C::st(buf, i * D.plane + idx, (float)(W[i] * (r - (double)D.rho_ref)));
+    for (int i = 0; i < 9; ++i)
+      C::st(buf, (uint32_t)(i * (uint32_t)D.plane + idx) * C::E, (float)(W[i] * (r - (double)D.rho_ref)));
     if (!D.isothermal)
       for (int i = 0; i < 9; ++i)
-        C::st(buf, (9 + i) * D.plane + idx, (float)(W[i] * (t - (double)D.T_ref)));
+        C::st(buf, (uint32_t)((9 + i) * (uint32_t)D.plane + idx) * C::E,
+              (float)(W[i] * (t - (double)D.T_ref)));
     if (D.bc_x == LBM_BCX_CHANNEL && x == D.nx - 1) {
       D.fold[b][0 * D.ny + y] = (float)(W[3] * (r - (double)D.rho_ref));
       D.fold[b][1 * D.ny + y] = (float)(W[6] * (r - (double)D.rho_ref));
@@ -560,11 +725,12 @@ __global__ void copy_kernel(float4* __restrict__ dst, const float4* __restrict__
     default: return hipErrorInvalidValue;                 \
   }
 
-hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, int grid, int phase,
-                           hipStream_t s) {
+hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, DevDomain* const* doms,
+                           int ndoms, int grid, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (grid <= 0 || grid > ntiles) grid = ntiles;
-#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_STEP>), dim3(grid), dim3(kWave), 0, s, tiles, ntiles, phase)
+  grid += kFinalizers;
+#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_STEP>), dim3(grid), dim3(kWave), 0, s, tiles, ntiles, doms, ndoms, phase)
   DISPATCH_STORE(storage, L)
 #undef L
   return hipGetLastError();
@@ -572,7 +738,7 @@ hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, int grid,
 
 hipError_t lbm_launch_readout(int storage, const Tile* tiles, int ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_READOUT>), dim3(ntiles), dim3(kWave), 0, s, tiles, ntiles, phase)
+#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_READOUT>), dim3(ntiles), dim3(kWave), 0, s, tiles, ntiles, (DevDomain* const*)nullptr, 0, phase)
   DISPATCH_STORE(storage, L)
 #undef L
   return hipGetLastError();

@@ -108,7 +108,7 @@ int validate(const lbm_params* p) {
 namespace {
 
 struct Layout {
-  size_t state, fold, psiw, Tw, heater, partials, rpart, rbar, ring, stepc, out, desc, tiles, total;
+  size_t state, fold, psiw, Tw, heater, partials, rpart, rbar, ring, stepc, out, desc, self, tiles, total;
   size_t state_bytes, fold_bytes;
 };
 
@@ -139,6 +139,7 @@ Layout layout_of(const lbm_params& p) {
   L.stepc = o; o += 256;
   L.out = o; o += 4 * align_up((size_t)p.nx * p.ny * sizeof(float), 256);
   L.desc = o; o += align_up(sizeof(DevDomain), 256);
+  L.self = o; o += 256;
   L.tiles = o; o += align_up(mt * sizeof(Tile), 256);
   L.total = o;
   return L;
@@ -232,6 +233,7 @@ void fill_desc(lbm_domain* d) {
   D.U_out = (float)U;
   D.inv_1pU = (float)(1.0 / (1.0 + U));
   D.in_geq = (float)(p.T_in * (1.0 + 3.0 * p.u_in * p.u_in));
+  D.inv_1mu = (float)(1.0 / (1.0 - p.u_in));
   D.rho_ref = (float)p.rho_ref;
   D.T_ref = (float)p.T_ref;
   D.T_iso = (float)p.T_iso;
@@ -240,10 +242,20 @@ void fill_desc(lbm_domain* d) {
 
 }  // namespace
 
+// Rows per tile: the requested value, or (auto) enough tiles to give every
+// SIMD of the 256 CUs about three waves, between 4 and 64 rows.
+int lbm_auto_rows(int nx, int ny) {
+  const int strips = (nx + kStripInterior - 1) / kStripInterior;
+  const long long want = 3072;
+  int rows = (int)((strips * (long long)ny + want - 1) / want);
+  rows = (rows + 3) / 4 * 4;
+  return std::min(64, std::max(kMinTileRows, rows));
+}
+
 int lbm_build_tiles(lbm_domain* d) {
   lbm_drop_graphs(d);
   const int nx = d->P.nx, ny = d->P.ny;
-  const int rows = std::max(kMinTileRows, d->rows);
+  const int rows = d->rows > 0 ? std::max(kMinTileRows, d->rows) : lbm_auto_rows(nx, ny);
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
   const int segs = (ny + rows - 1) / rows;
   d->tiles_h.clear();
@@ -281,7 +293,7 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   lbm_domain* d = new (std::nothrow) lbm_domain();
   if (!d) return lbm_fail(LBM_E_NOMEM, "host allocation failed");
   d->P = *p;
-  d->rows = kDefaultTileRows;
+  d->rows = 0;  // automatic
   if (hip_stream) {
     d->stream = (hipStream_t)hip_stream;
     d->own_stream = false;
@@ -335,7 +347,12 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   for (int k = 0; k < 4; ++k) D.out[k] = (float*)(m + L.out + k * ob);
   D.parity = 0;
   d->dev = (DevDomain*)(m + L.desc);
+  d->self_d = (DevDomain**)(m + L.self);
   d->tiles_d = (Tile*)(m + L.tiles);
+  if (hipMemcpy(d->self_d, &d->dev, sizeof(DevDomain*), hipMemcpyHostToDevice) != hipSuccess) {
+    lbm_destroy(d);
+    return lbm_fail(LBM_E_DEVICE, "descriptor upload failed");
+  }
   // default walls: inlet temperature, neutral wall (rho_w = rho of the initial
   // uniform state is not known here -> zero pseudopotential until set)
   std::vector<float> z(p->nx, 0.f), tw(p->nx, (float)p->T_in);
@@ -454,7 +471,7 @@ extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* 
 int lbm_enqueue_steps(lbm_domain* d, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
     const int phase = (int)((d->step + k) & 1) ^ d->host.parity;
-    HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->grid, phase, d->stream));
+    HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->self_d, 1, d->grid, phase, d->stream));
   }
   d->step += nsteps;
   return LBM_OK;
@@ -722,7 +739,7 @@ extern "C" int lbm_set_tile_rows(lbm_domain* d, int rows) {
     double tot[kPartials] = {0};
     for (int t = 0; t < d->ntiles; ++t)
       for (int q = 0; q < kPartials; ++q) tot[q] += old[(size_t)t * kPartials + q];
-    d->rows = rows == 0 ? kDefaultTileRows : std::max(rows, kMinTileRows);
+    d->rows = rows == 0 ? 0 : std::max(rows, kMinTileRows);
     int rc = lbm_build_tiles(d);
     if (rc) return rc;
     std::vector<double> nw((size_t)d->ntiles * kPartials, 0.0);
@@ -730,7 +747,7 @@ extern "C" int lbm_set_tile_rows(lbm_domain* d, int rows) {
     HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice));
     return LBM_OK;
   }
-  d->rows = rows == 0 ? kDefaultTileRows : std::max(rows, kMinTileRows);
+  d->rows = rows == 0 ? 0 : std::max(rows, kMinTileRows);
   int rc = lbm_build_tiles(d);
   if (rc) return rc;
   if (d->inited) {
