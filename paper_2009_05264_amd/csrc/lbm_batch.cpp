@@ -58,7 +58,7 @@ static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int)
 
 static int enqueue_domain_phase(void* ctx, int phase) {
   lbm_domain* d = (lbm_domain*)ctx;
-  HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->self_d, 1, d->grid, phase, d->stream));
+  HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->fins_d, kFin, d->grid, phase, d->stream));
   return LBM_OK;
 }
 
@@ -93,8 +93,8 @@ struct lbm_batch {
     Tile* tiles_d = nullptr;
     int ntiles = 0;
     int grid = 0;
-    DevDomain** doms_d = nullptr;  // domains whose reductions this launch finalizes
-    int ndoms = 0;
+    FinEntry* fins_d = nullptr;  // finalizer waves of the group's domains
+    int nfins = 0;
   };
   std::vector<Group> groups;
   GraphEntry graph;
@@ -107,26 +107,26 @@ struct lbm_batch {
 static int build_groups(lbm_batch* b) {
   for (auto& g : b->groups) {
     if (g.tiles_d) (void)hipFree(g.tiles_d);
-    if (g.doms_d) (void)hipFree(g.doms_d);
+    if (g.fins_d) (void)hipFree(g.fins_d);
   }
   b->groups.clear();
   std::map<int, std::vector<Tile>> by;
-  std::map<int, std::vector<DevDomain*>> dby;
+  std::map<int, std::vector<FinEntry>> fby;
   for (lbm_domain* d : b->doms) {
     auto& v = by[d->P.storage];
     v.insert(v.end(), d->tiles_h.begin(), d->tiles_h.end());
-    dby[d->P.storage].push_back(d->dev);
+    for (int f = 0; f < kFin; ++f) fby[d->P.storage].push_back(FinEntry{d->dev, f, 0});
   }
   for (auto& kv : by) {
     lbm_batch::Group g;
     g.storage = kv.first;
     g.ntiles = (int)kv.second.size();
-    const auto& dl = dby[kv.first];
-    g.ndoms = (int)dl.size();
+    const auto& fl = fby[kv.first];
+    g.nfins = (int)fl.size();
     HIPCHECK(hipMalloc(&g.tiles_d, g.ntiles * sizeof(Tile)));
     HIPCHECK(hipMemcpy(g.tiles_d, kv.second.data(), g.ntiles * sizeof(Tile), hipMemcpyHostToDevice));
-    HIPCHECK(hipMalloc(&g.doms_d, g.ndoms * sizeof(DevDomain*)));
-    HIPCHECK(hipMemcpy(g.doms_d, dl.data(), g.ndoms * sizeof(DevDomain*), hipMemcpyHostToDevice));
+    HIPCHECK(hipMalloc(&g.fins_d, g.nfins * sizeof(FinEntry)));
+    HIPCHECK(hipMemcpy(g.fins_d, fl.data(), g.nfins * sizeof(FinEntry), hipMemcpyHostToDevice));
     b->groups.push_back(g);
   }
   return LBM_OK;
@@ -135,7 +135,7 @@ static int build_groups(lbm_batch* b) {
 static int enqueue_batch_phase(void* ctx, int phase) {
   lbm_batch* b = (lbm_batch*)ctx;
   for (auto& g : b->groups)
-    HIPCHECK(lbm_launch_step(g.storage, g.tiles_d, g.ntiles, g.doms_d, g.ndoms, g.grid, phase, b->stream));
+    HIPCHECK(lbm_launch_step(g.storage, g.tiles_d, g.ntiles, g.fins_d, g.nfins, g.grid, phase, b->stream));
   return LBM_OK;
 }
 
@@ -318,7 +318,7 @@ extern "C" int lbm_batch_destroy(lbm_batch* b) {
   drop_batch_graph(b);
   for (auto& g : b->groups) {
     if (g.tiles_d) (void)hipFree(g.tiles_d);
-    if (g.doms_d) (void)hipFree(g.doms_d);
+    if (g.fins_d) (void)hipFree(g.fins_d);
   }
   for (lbm_domain* d : b->doms) {
     d->in_batch = false;

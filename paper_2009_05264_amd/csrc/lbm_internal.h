@@ -9,6 +9,7 @@ constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kStripInterior = 60;  // interior columns per wave (64 - 2 - 2 halo)
 constexpr int kPartials = 8;        // doubles per tile partial
 constexpr int kRing = 4096;         // per-step diagnostics records kept on device
+constexpr int kFin = 16;            // finalizer waves per domain (level-1 slices)
 
 // Partial sums of one tile, in this order.
 enum { P_MASS = 0, P_ENERGY, P_HEATQ, P_VAPOR, P_CLAMP, P_NONFINITE, P_PIN, P_POUT };
@@ -45,14 +46,23 @@ struct DevDomain {
   const float* psiw[2]; // pseudopotential of the false wall density, S and N, [nx]
   const float* Tw[2];   // wall temperature, S and N, [nx]
   const int* heater;    // bottom heater flags [nx]
-  double* partials[2];  // [ntiles][kPartials], A/B
-  double* rbar;         // [2] lagged mean density slots
+  double* partials[2];  // [kPartials][pstride] per launch parity (SoA over tiles)
+  double* l1[2];        // [kFin][kPartials] slice sums of the partials, per parity
+  double* rbar;         // scratch for read-out reductions
   DiagRec* ring;        // [kRing]
   long long* step_dev;  // device step counter (written only by the first tile)
-  double* readout_partials;  // [ntiles][kPartials]
+  double* readout_partials;  // [kPartials][pstride]
+  int pstride;          // tile capacity of the partial-sum arrays
+  int pad6;
   float* out[4];        // read-out fields rho, ux, uy, T [ny][nx]
   int parity;           // storage buffer parity offset
   int pad5;
+};
+
+// One finalizer wave: slice f of domain d's per-tile partial sums.
+struct FinEntry {
+  DevDomain* d;
+  int f, pad;
 };
 
 // One tile of the step kernel: a 64-lane strip starting two columns left of
@@ -69,10 +79,10 @@ enum StepMode { MODE_STEP = 0, MODE_READOUT = 1 };
 
 // Launch wrappers (lbm_kernels.hip).
 hipError_t lbm_launch_step(int storage, const lbm::Tile* tiles, int ntiles,
-                           lbm::DevDomain* const* doms, int ndoms, int grid, int phase, hipStream_t s);
+                           const lbm::FinEntry* fins, int nfins, int grid, int phase, hipStream_t s);
 hipError_t lbm_launch_readout(int storage, const lbm::Tile* tiles, int ntiles, int phase,
                               hipStream_t s);
-hipError_t lbm_launch_finalize(lbm::DevDomain* d, const double* partials, int ntiles, double* out8,
+hipError_t lbm_launch_finalize(const double* partials, int pstride, int ntiles, double* out8,
                                hipStream_t s);
 hipError_t lbm_launch_init(int storage, lbm::DevDomain* dhost_copy_dev, const lbm::DevDomain& dh,
                            const double* rho0, const double* T0, double rho_u, double T_u,

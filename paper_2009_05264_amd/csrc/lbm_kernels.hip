@@ -18,9 +18,9 @@
 // FP16 or BF16 (template parameter).
 //
 // Reductions for the diagnostics and for the mean density of the buoyancy
-// force are fixed-order FP64: each tile writes its partial sums; the first
-// tile of each domain sums the previous launch's partials at the start of the
-// next launch (kernel boundaries order the two).
+// force are fixed-order FP64: each tile writes its partial sums; in the next
+// launch kFin finalizer waves per domain reduce slices of them, and the
+// launch after that sums the slices (kernel boundaries order every step).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -90,8 +90,13 @@ typedef const DevDomain AS4& DRef;
 // wave-uniform byte offset per distribution plane (SGPR) and one per-lane
 // byte offset per row (VGPR).
 typedef __amdgpu_buffer_rsrc_t Rsrc;
+// Byte offsets at or above kRange are outside the resource: stores there are
+// dropped and loads return 0 (raw-buffer bounds check), which lets lanes
+// without a node of their own issue the same store instruction unmasked.
+constexpr int kRange = 0x7FFFFF00;
+constexpr int kDrop = 0x7FFFFF00;
 __device__ __forceinline__ Rsrc make_rsrc(const void* base) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7FFFFFFF, 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, kRange, 0x00020000);
 }
 template <int S>
 struct BufIO;
@@ -144,6 +149,8 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return r < 0 ? r + n : r;
 }
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+// Periodic wrap of v in [-n, 2n).
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // Peng-Robinson EOS (Eq. 12), pseudopotential (Eq. 11), (dp/dT)_rho.
 __device__ __forceinline__ void eos(DRef D, float rho, float T, float& p, float& psi,
@@ -163,124 +170,39 @@ __device__ __forceinline__ void eos(DRef D, float rho, float T, float& p, float&
   dpdT = rho * D.R * r1 + ar2 * D.kappa * sa * rcp(s * D.Tc);
 }
 
-// Byte offset of distribution plane i (0-8 f, 9-17 g) at element idx.
-template <int S>
-__device__ __forceinline__ uint32_t boff(DRef D, int i, uint32_t idx) {
-  return (uint32_t)(i * (uint32_t)D.plane + idx) * (uint32_t)Codec<S>::E;
-}
-
-// Convective outlet for direction I (memory slot M) at node (nx-1, y): the
-// value pulled this step at (nx-2, y), i.e. the post-collision value of
-// direction I at (nx-1, y - cy_I), blended with the previous step's value.
-template <int S, int I, int M>
-__device__ __forceinline__ void outlet_dir(DRef D, gptr src, const float* fold, int y, bool thermal,
-                                           float h[9], float k[9]) {
-  using C = Codec<S>;
-  const int ny = D.ny;
-  const int ys = y - CY[I];
-  if (D.bc_y == LBM_BCY_WALLS && (ys < 0 || ys >= ny)) return;  // wall rule already applied
-  const int ysw = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-  const uint32_t sidx = (uint32_t)(ysw * D.pitch + (D.nx - 1));
-  const float hn = C::ld(src, boff<S>(D, I, sidx));
-  h[I] = (fold[M * ny + y] + D.U_out * hn) * D.inv_1pU;
-  if (thermal) k[I] = C::ld(src, boff<S>(D, 9 + I, sidx));
-}
-
-// Pull of an interior node (every source inside the domain).  The resource
-// base sits one row and one column before the buffer, so the source of
-// direction i is  plane offset (SGPR) + row offset of y - cy_i (one of three
-// VGPRs) + (1 - cx_i) elements (immediate).
+// Raw-buffer pull.  The resource base sits one row and one column before
+// the buffer, so the source of direction i is: plane offset (SGPR) + the
+// row-and-column offset of its source row at the lane's column (VGPR) +
+// (1 - cx_i) elements (immediate).  vf[i] / vg[i] are the per-lane offsets of
+// the f / g source of direction i, so[i] the plane offsets (0-8 f, 9-17 g).
 template <int S, int I>
-__device__ __forceinline__ float ld_dir(Rsrc rs, const int vrow[3], int soff) {
-  constexpr int m = 1 - CY[I];
+__device__ __forceinline__ float ld_dir(Rsrc rs, int voff, int soff) {
   constexpr int imm = 1 - CX[I];
-  return BufIO<S>::template ld<imm>(rs, vrow[m], soff);
+  return BufIO<S>::template ld<imm>(rs, voff, soff);
 }
 
-template <int S>
-__device__ __forceinline__ void pull_fast(Rsrc rs, const int sp[18], const int vrow[3], bool thermal,
-                                          float h[9], float k[9]) {
-  h[0] = ld_dir<S, 0>(rs, vrow, sp[0]);
-  h[1] = ld_dir<S, 1>(rs, vrow, sp[1]);
-  h[2] = ld_dir<S, 2>(rs, vrow, sp[2]);
-  h[3] = ld_dir<S, 3>(rs, vrow, sp[3]);
-  h[4] = ld_dir<S, 4>(rs, vrow, sp[4]);
-  h[5] = ld_dir<S, 5>(rs, vrow, sp[5]);
-  h[6] = ld_dir<S, 6>(rs, vrow, sp[6]);
-  h[7] = ld_dir<S, 7>(rs, vrow, sp[7]);
-  h[8] = ld_dir<S, 8>(rs, vrow, sp[8]);
-  if (thermal) {
-    k[0] = ld_dir<S, 0>(rs, vrow, sp[9]);
-    k[1] = ld_dir<S, 1>(rs, vrow, sp[10]);
-    k[2] = ld_dir<S, 2>(rs, vrow, sp[11]);
-    k[3] = ld_dir<S, 3>(rs, vrow, sp[12]);
-    k[4] = ld_dir<S, 4>(rs, vrow, sp[13]);
-    k[5] = ld_dir<S, 5>(rs, vrow, sp[14]);
-    k[6] = ld_dir<S, 6>(rs, vrow, sp[15]);
-    k[7] = ld_dir<S, 7>(rs, vrow, sp[16]);
-    k[8] = ld_dir<S, 8>(rs, vrow, sp[17]);
-  }
-}
-
-// Pull of node (xc, y) from the post-collision buffer with the boundary
-// rules (bounce-back / anti-bounce-back at wall rows, Zou-He inlet,
-// convective outlet).  xc in [0, nx), y in [0, ny).
-template <int S>
-__device__ __forceinline__ void pull(DRef D, gptr src, const float* fold, int xc, int y,
-                                     bool thermal, float h[9], float k[9]) {
-  using C = Codec<S>;
-  const int nx = D.nx, ny = D.ny;
-  const uint32_t own = (uint32_t)(y * D.pitch + xc);
-  const bool walls = D.bc_y == LBM_BCY_WALLS;
-  const bool chan = D.bc_x == LBM_BCX_CHANNEL;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    int xs = xc - CX[i];
-    int ys = y - CY[i];
-    if (walls && (ys < 0 || ys >= ny)) {
-      const int o = OPP[i];
-      const int xm = chan ? clampi(xs, 0, nx - 1) : (xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs));
-      h[i] = C::ld(src, boff<S>(D, o, own));
-      if (thermal) {
-        const float Tw = (ys < 0 ? D.Tw[0] : D.Tw[1])[xm];
-        k[i] = -C::ld(src, boff<S>(D, 9 + o, own)) + 2.f * WF[i] * (Tw - D.T_ref);
-      }
-    } else {
-      ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-      if (!chan) xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-      if (xs >= 0 && xs < nx) {
-        const uint32_t idx = (uint32_t)(ys * D.pitch + xs);
-        h[i] = C::ld(src, boff<S>(D, i, idx));
-        if (thermal) k[i] = C::ld(src, boff<S>(D, 9 + i, idx));
-      } else {
-        h[i] = 0.f;  // ghost source: set by the inlet / outlet rule below
-        k[i] = 0.f;
-      }
-    }
-  }
-  if (!chan) return;
-  if (xc == 0) {
-    // Zou-He velocity inlet; unknowns are 1, 5, 8 unless a wall row is the source.
-    const float u = D.u_in;
-    const float rin = (D.rho_ref + h[0] + h[2] + h[4] + 2.f * (h[3] + h[6] + h[7])) * D.inv_1mu;
-    const bool unk5 = !(walls && y - 1 < 0);
-    const bool unk8 = !(walls && y + 1 >= ny);
-    const float d24 = 0.5f * (h[2] - h[4]);
-    h[1] = h[3] + (2.f / 3.f) * rin * u;
-    if (unk5) h[5] = h[7] - d24 + rin * u * (1.f / 6.f);
-    if (unk8) h[8] = h[6] + d24 + rin * u * (1.f / 6.f);
-    if (thermal) {
-      const float gin = D.in_geq - D.T_ref;
-      k[1] = -C::ld(src, boff<S>(D, 9 + 3, own)) + 2.f * WF[1] * gin;
-      if (unk5) k[5] = -C::ld(src, boff<S>(D, 9 + 7, own)) + 2.f * WF[5] * gin;
-      if (unk8) k[8] = -C::ld(src, boff<S>(D, 9 + 6, own)) + 2.f * WF[8] * gin;
-    }
-  }
-  if (xc == nx - 1) {
-    // Convective outlet for 3, 6, 7 from the values just pulled at nx-2.
-    outlet_dir<S, 3, 0>(D, src, fold, y, thermal, h, k);
-    outlet_dir<S, 6, 1>(D, src, fold, y, thermal, h, k);
-    outlet_dir<S, 7, 2>(D, src, fold, y, thermal, h, k);
+template <int S, bool TH>
+__device__ __forceinline__ void pull_dirs(Rsrc rs, const int (&vf)[9], const int (&vg)[9],
+                                          const int (&so)[18], float (&h)[9], float (&k)[9]) {
+  h[0] = ld_dir<S, 0>(rs, vf[0], so[0]);
+  h[1] = ld_dir<S, 1>(rs, vf[1], so[1]);
+  h[2] = ld_dir<S, 2>(rs, vf[2], so[2]);
+  h[3] = ld_dir<S, 3>(rs, vf[3], so[3]);
+  h[4] = ld_dir<S, 4>(rs, vf[4], so[4]);
+  h[5] = ld_dir<S, 5>(rs, vf[5], so[5]);
+  h[6] = ld_dir<S, 6>(rs, vf[6], so[6]);
+  h[7] = ld_dir<S, 7>(rs, vf[7], so[7]);
+  h[8] = ld_dir<S, 8>(rs, vf[8], so[8]);
+  if (TH) {
+    k[0] = ld_dir<S, 0>(rs, vg[0], so[9]);
+    k[1] = ld_dir<S, 1>(rs, vg[1], so[10]);
+    k[2] = ld_dir<S, 2>(rs, vg[2], so[11]);
+    k[3] = ld_dir<S, 3>(rs, vg[3], so[12]);
+    k[4] = ld_dir<S, 4>(rs, vg[4], so[13]);
+    k[5] = ld_dir<S, 5>(rs, vg[5], so[14]);
+    k[6] = ld_dir<S, 6>(rs, vg[6], so[15]);
+    k[7] = ld_dir<S, 7>(rs, vg[7], so[16]);
+    k[8] = ld_dir<S, 8>(rs, vg[8], so[17]);
   }
 }
 
@@ -353,159 +275,352 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Fixed-order sum of ntiles partial records by one wave; lane 0 gets it.
-__device__ __forceinline__ void sum_partials(const double* parts, int ntiles, double out[kPartials]) {
+// Fixed-order sum of tiles [t0, t1) of SoA partial sums by one wave; every
+// lane gets the result.  Loads are issued four tiles at a time per lane.
+__device__ __forceinline__ void sum_partials(const double* parts, int stride, int t0, int t1,
+                                             double out[kPartials]) {
   const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
-  for (int q = 0; q < kPartials; ++q) out[q] = 0.0;
-  for (int t = lane; t < ntiles; t += kWave) {
-#pragma unroll
-    for (int q = 0; q < kPartials; ++q) out[q] += parts[(long long)t * kPartials + q];
+  for (int q = 0; q < kPartials; ++q) {
+    const double* a = parts + (long long)q * stride;
+    double acc = 0.0;
+    int t = t0 + lane;
+    for (; t + 3 * kWave < t1; t += 4 * kWave) {
+      const double v0 = a[t], v1 = a[t + kWave], v2 = a[t + 2 * kWave], v3 = a[t + 3 * kWave];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+    }
+    for (; t < t1; t += kWave) acc += a[t];
+    out[q] = wave_sum(acc);
   }
-#pragma unroll
-  for (int q = 0; q < kPartials; ++q) out[q] = wave_sum(out[q]);
 }
 
-// Per-lane data of the row whose force is being formed (stage 2) and of the
-// row below it (stage 3).
-struct RowA {  // row r: just pulled
-  float h[9], k[9];
-  float drho, jx, jy, dT, psi, A, B, dpdT;
-};
-
-template <int S, int MODE>
-__device__ void run_tile(const Tile AS4& tl, int gphase) {
+// One wavefront's march over a tile.  Rolling per-lane state: row r just
+// pulled (a), row r-1 (b: force, u_act, f collision), row r-2 (c: source and
+// g collision), and u_act,y of row r-3 (d).  The loop body is instantiated
+// with compile-time stage flags so that the steady-state iteration is one
+// straight path with a fixed number of loads and stores.
+//
+// EDGE = false: every source of the tile lies inside the domain.  EDGE =
+// true: the same raw-buffer pull with the boundary rules folded into the
+// addresses -- periodic rows wrap in the row offsets; a wall row reads the
+// opposite direction at the node itself (bounce-back) through its plane
+// offsets; lanes of the first / last column correct their x-sources
+// (periodic wrap, or the inlet / outlet sources); the value-level parts of
+// the rules (anti-bounce-back temperatures, Zou-He, convective blend) are
+// applied when the row is consumed.
+template <int S, int MODE, bool EDGE, bool TH>
+struct TileRun {
   using C = Codec<S>;
-  DRef D = *(const DevDomain AS4*)tl.d;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int phase = gphase ^ D.parity;
-  const int nx = D.nx, ny = D.ny;
-  const bool chan = D.bc_x == LBM_BCX_CHANNEL;
-  const bool walls = D.bc_y == LBM_BCY_WALLS;
-  const bool thermal = !D.isothermal;
-  gptr src = as_global(D.buf[phase]);
-  gptr_w dst = as_global(D.buf[phase ^ 1]);
-  const float* fold = D.fold[phase];
-  float* fold_dst = D.fold[phase ^ 1];
-
-  const int x = tl.x0 - 2 + lane;
-  const int xc = chan ? clampi(x, 0, nx - 1) : wrap(x, nx);
-  const bool interior = lane >= 2 && lane < kWave - 2 && x < nx;
-  const float gbar = (float)((double)D.rho_ref - D.rbar[phase]);  // rho_ref - rho_bar
-  const bool xlo = chan && x == 0, xhi = chan && x == nx - 1;
-
-  double acc_mass = 0.0, acc_energy = 0.0, acc_q = 0.0;
+  DRef D;
+  const Tile AS4& tl;
+  int lane, phase, nx, ny, x, xc;
+  bool chan, walls, interior, xlo, xhi, has_out;
+  const float* fold;
+  float* fold_dst;
+  Rsrc rs, rd;
+  int pitch, sst[18];
+  float gbar;
+  int r_end;
+  // boundary tiles: -1 in lanes whose column is 0 (mL) / nx-1 (mR)
+  int mL = 0, mR = 0;
+  // wall constants, south (S) and north (N): psi of the false wall density
+  // at xc and the wall temperature at xc, m(xc-1), m(xc+1)
+  float psiS = 0.f, twS0 = 0.f, twS1 = 0.f, twS2 = 0.f;
+  float psiN = 0.f, twN0 = 0.f, twN1 = 0.f, twN2 = 0.f;
+  bool heat = false;
+  Rsrc rfo, rfd;  // outlet memory, this launch's source and destination
+  // reductions
+  double acc_mass = 0.0, acc_energy = 0.0, acc_q = 0.0, acc_pin = 0.0, acc_pout = 0.0;
   int acc_vap = 0, acc_clamp = 0, acc_nf = 0;
-  double acc_pin = 0.0, acc_pout = 0.0;
-
-  // row r (a), row r-1 (b), row r-2 (c); s* = wall row flags
-  RowA a;
+  // prefetched rows, double-buffered: a loaded register is first touched one
+  // iteration after its load was issued; pfo: outlet memory of that row
+  float ph[2][9], pk[2][9], pfo[2][3];
+  // row a (r)
+  float a_drho = 0.f, a_jx = 0.f, a_jy = 0.f, a_dT = 0.f, a_psi = 0.f, a_A = 0.f, a_B = 0.f, a_dpdT = 0.f;
   bool sa = false;
+  // row b (r-1)
   float bh[9], bk[9];
   float b_drho = 0.f, b_jx = 0.f, b_jy = 0.f, b_dT = 0.f, b_psi = 0.f, b_A = 0.f, b_B = 0.f, b_dpdT = 0.f;
   bool sb = false;
+  // row c (r-2)
   float ck[9];
   float c_A = 0.f, c_B = 0.f, c_dT = 0.f, c_dpdT = 0.f, c_irho = 0.f, c_uax = 0.f, c_uay = 0.f;
   bool sc = false;
-  float d_uay = 0.f;  // u_act,y of row r-3
+  // row d (r-3)
+  float d_uay = 0.f;
   bool sd = false;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) bh[i] = bk[i] = ck[i] = 0.f;
 
-  const int r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
-  // The pull of row r + 1 is issued before row r is processed, so its memory
-  // latency overlaps the arithmetic of the current iteration.
-  float nh[9], nk[9];
+  __device__ __forceinline__ TileRun(const Tile AS4& t, int gphase)
+      : D(*(const DevDomain AS4*)t.d), tl(t) {
+    lane = threadIdx.x & (kWave - 1);
+    phase = gphase ^ D.parity;
+    nx = D.nx;
+    ny = D.ny;
+    chan = EDGE && D.bc_x == LBM_BCX_CHANNEL;
+    walls = EDGE && D.bc_y == LBM_BCY_WALLS;
+    fold = D.fold[phase];
+    fold_dst = D.fold[phase ^ 1];
+    x = tl.x0 - 2 + lane;
+    xc = !EDGE ? x : (chan ? clampi(x, 0, nx - 1) : wrap(x, nx));
+    interior = lane >= 2 && lane < kWave - 2 && x < nx;
+    xlo = chan && x == 0;
+    xhi = chan && x == nx - 1;
+    has_out = chan && tl.x0 + kWave - 3 >= nx - 1;
+    mL = EDGE && xc == 0 ? -1 : 0;
+    mR = EDGE && xc == nx - 1 ? -1 : 0;
+    pitch = D.pitch;
+    constexpr int E = C::E;
+    const int plane = (int)D.plane;
+    rs = make_rsrc((const char*)D.buf[phase] - (pitch + 1) * E);
+    rd = make_rsrc(D.buf[phase ^ 1]);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) nh[i] = nk[i] = 0.f;
-  // A tile whose 64 columns and their x-neighbours lie inside the domain
-  // pulls interior rows with no boundary logic, through buffer resources.
-  const bool xfast = tl.x0 >= 3 && tl.x0 + kWave - 2 < nx;
-  constexpr int E = C::E;
-  const int pitch = D.pitch;
-  const int plane = (int)D.plane;
-  const Rsrc rs = make_rsrc((const char*)D.buf[phase] - (pitch + 1) * E);
-  const Rsrc rd = make_rsrc(D.buf[phase ^ 1]);
-  int sst[18];  // byte offset of each distribution plane
+    for (int i = 0; i < 18; ++i) sst[i] = i * plane * E;
+    // mean density two states back: sum of the level-1 slices written by the
+    // previous launch's finalizers
+    double mass = lane < kFin ? D.l1[phase][lane * kPartials + P_MASS] : 0.0;
+    mass = wave_sum(mass);
+    gbar = (float)((double)D.rho_ref - mass / ((double)nx * (double)ny));
+    r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
 #pragma unroll
-  for (int i = 0; i < 18; ++i) sst[i] = i * plane * E;
-  auto fetch = [&](int rr) {
-    if (xfast && rr >= 1 && rr <= ny - 2) {
+    for (int i = 0; i < 9; ++i) ph[0][i] = pk[0][i] = ph[1][i] = pk[1][i] = bh[i] = bk[i] = ck[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pfo[0][i] = pfo[1][i] = 0.f;
+    if (EDGE) {
+      // Every load and store of a boundary tile is issued unconditionally
+      // (offset kDrop where it has nothing to move), so that the march keeps
+      // a fixed count of memory operations per row.
+      rfo = make_rsrc(fold);
+      rfd = make_rsrc(fold_dst);
+      const bool needS = walls && tl.y0 - 2 <= 0, needN = walls && r_end >= ny - 1;
+      const int xm = chan ? max(xc - 1, 0) : (xc == 0 ? nx - 1 : xc - 1);
+      const int xp = chan ? min(xc + 1, nx - 1) : (xc == nx - 1 ? 0 : xc + 1);
+      const int oS = needS ? xc * 4 : kDrop, oN = needN ? xc * 4 : kDrop;
+      const int mS = needS ? xm * 4 : kDrop, mN = needN ? xm * 4 : kDrop;
+      const int pS = needS ? xp * 4 : kDrop, pN = needN ? xp * 4 : kDrop;
+      const Rsrc rT0 = make_rsrc(D.Tw[0]), rT1 = make_rsrc(D.Tw[1]);
+      const Rsrc rP0 = make_rsrc(D.psiw[0]), rP1 = make_rsrc(D.psiw[1]);
+      psiS = ld32(rP0, oS);
+      twS0 = ld32(rT0, oS);
+      twS1 = ld32(rT0, mS);
+      twS2 = ld32(rT0, pS);
+      psiN = ld32(rP1, oN);
+      twN0 = ld32(rT1, oN);
+      twN1 = ld32(rT1, mN);
+      twN2 = ld32(rT1, pN);
+      const int oH = walls && tl.y0 == 0 ? xc * 4 : kDrop;
+      heat = __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(D.heater), oH, 0, 0) != 0u;
+    }
+  }
+
+  static __device__ __forceinline__ float ld32(Rsrc r, int voff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+  }
+
+  template <int B>
+  __device__ __forceinline__ void fetch(int rr) {
+    constexpr int E = C::E;
+    int vf[9], vg[9], so[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) so[i] = sst[i];
+    if (!EDGE) {
       const int v0 = (rr * pitch + xc) * E;
-      const int vrow[3] = {v0, v0 + pitch * E, v0 + 2 * pitch * E};
-      pull_fast<S>(rs, sst, vrow, thermal, nh, nk);
+      const int vr[3] = {v0, v0 + pitch * E, v0 + 2 * pitch * E};
+#pragma unroll
+      for (int i = 0; i < 9; ++i) vf[i] = vg[i] = vr[1 - CY[i]];
+    } else {
+      // a solid row (beyond a wall) moves nothing: every offset is kDrop
+      const bool solid = walls && (rr < 0 || rr >= ny);
+      const int ro = walls ? clampi(rr, 0, ny - 1) : wrap1(rr, ny);
+      const bool wS = walls && ro == 0, wN = walls && ro == ny - 1;
+      const int rsr = wS ? ro : (ro == 0 ? ny - 1 : ro - 1);
+      const int rnr = wN ? ro : (ro == ny - 1 ? 0 : ro + 1);
+      const int PE = pitch * E;
+      const int R0 = (rsr + 1) * PE, R1 = (ro + 1) * PE, R2 = (rnr + 1) * PE;
+      const int xe = xc * E;
+      const int vr[3] = {solid ? kDrop : xe + R0, solid ? kDrop : xe + R1, solid ? kDrop : xe + R2};
+      const int mLr = solid ? 0 : mL, mRr = solid ? 0 : mR;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) vf[i] = vg[i] = vr[1 - CY[i]];
+      // bounce-back sources: the opposite direction at the node itself
+      if (wS) {
+        so[2] = sst[4];
+        so[5] = sst[7] + E;
+        so[6] = sst[8] - E;
+        so[11] = sst[13];
+        so[14] = sst[16] + E;
+        so[15] = sst[17] - E;
+      }
+      if (wN) {
+        so[4] = sst[2];
+        so[7] = sst[5] - E;
+        so[8] = sst[6] + E;
+        so[13] = sst[11];
+        so[16] = sst[14] - E;
+        so[17] = sst[15] + E;
+      }
+      const int P = sst[1];
+      int cL1, cL5, cL8, gL1, gL5, gL8, cR3, cR6, cR7;
+      if (chan) {
+        // inlet column: the f slots of 1, 5, 8 (replaced by Zou-He) carry g
+        // of 3, 7, 6 at the node itself for the anti-bounce-back rule; the g
+        // slots keep their in-buffer ghost source.  Outlet column: the
+        // sources of 3, 6, 7 move from column nx to column nx-1.
+        cL1 = TH ? 11 * P + E : 0;
+        cL5 = (TH && !wS) ? 11 * P + E + (R1 - R0) : 0;
+        cL8 = (TH && !wN) ? 7 * P + E + (R1 - R2) : 0;
+        gL1 = gL5 = gL8 = 0;
+        cR3 = -E;
+        cR6 = wS ? 0 : -E;
+        cR7 = wN ? 0 : -E;
+      } else {
+        const int W = nx * E;
+        cL1 = W;
+        cL5 = wS ? 0 : W;
+        cL8 = wN ? 0 : W;
+        gL1 = cL1;
+        gL5 = cL5;
+        gL8 = cL8;
+        cR3 = -W;
+        cR6 = wS ? 0 : -W;
+        cR7 = wN ? 0 : -W;
+      }
+      vf[1] += mLr & cL1;
+      vf[5] += mLr & cL5;
+      vf[8] += mLr & cL8;
+      vg[1] += mLr & gL1;
+      vg[5] += mLr & gL5;
+      vg[8] += mLr & gL8;
+      vf[3] += mRr & cR3;
+      vf[6] += mRr & cR6;
+      vf[7] += mRr & cR7;
+      vg[3] += mRr & cR3;
+      vg[6] += mRr & cR6;
+      vg[7] += mRr & cR7;
+      const int vo = has_out && !solid ? ro * 4 : kDrop;
+      pfo[B][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 0, 0));
+      pfo[B][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, ny * 4, 0));
+      pfo[B][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 2 * ny * 4, 0));
     }
-    else if (!(walls && (rr < 0 || rr >= ny))) {
-      pull<S>(D, src, fold, xc, walls ? rr : wrap(rr, ny), thermal, nh, nk);
+    pull_dirs<S, TH>(rs, vf, vg, so, ph[B], pk[B]);
+  }
+
+  // Value-level boundary rules of row r (own row ro) on the pulled values.
+  __device__ __forceinline__ void fix_row(int ro, float* h, float* k, const float* fo) {
+    const bool wS = walls && ro == 0, wN = walls && ro == ny - 1;
+    if (TH && wS) {
+      const float dT0 = twS0 - D.T_ref, dTm = twS1 - D.T_ref, dTp = twS2 - D.T_ref;
+      k[2] = -k[2] + 2.f * WF[2] * dT0;
+      k[5] = -k[5] + 2.f * WF[5] * dTm;
+      k[6] = -k[6] + 2.f * WF[6] * dTp;
     }
-  };
-  fetch(tl.y0 - 2);
-  for (int r = tl.y0 - 2; r <= r_end; ++r) {
+    if (TH && wN) {
+      const float dT0 = twN0 - D.T_ref, dTm = twN1 - D.T_ref, dTp = twN2 - D.T_ref;
+      k[4] = -k[4] + 2.f * WF[4] * dT0;
+      k[7] = -k[7] + 2.f * WF[7] * dTp;
+      k[8] = -k[8] + 2.f * WF[8] * dTm;
+    }
+    if (chan && mL) {
+      // Zou-He velocity inlet; anti-bounce-back inlet temperature
+      const float u = D.u_in;
+      if (TH) {
+        const float gin = D.in_geq - D.T_ref;
+        k[1] = -h[1] + 2.f * WF[1] * gin;
+        if (!wS) k[5] = -h[5] + 2.f * WF[5] * gin;
+        if (!wN) k[8] = -h[8] + 2.f * WF[8] * gin;
+      }
+      const float rin = (D.rho_ref + h[0] + h[2] + h[4] + 2.f * (h[3] + h[6] + h[7])) * D.inv_1mu;
+      const float d24 = 0.5f * (h[2] - h[4]);
+      h[1] = h[3] + (2.f / 3.f) * rin * u;
+      if (!wS) h[5] = h[7] - d24 + rin * u * (1.f / 6.f);
+      if (!wN) h[8] = h[6] + d24 + rin * u * (1.f / 6.f);
+    }
+    if (chan && mR) {
+      // convective outlet: blend with the previous step's value
+      h[3] = (fo[0] + D.U_out * h[3]) * D.inv_1pU;
+      if (!wS) h[6] = (fo[1] + D.U_out * h[6]) * D.inv_1pU;
+      if (!wN) h[7] = (fo[2] + D.U_out * h[7]) * D.inv_1pU;
+    }
+  }
+
+  // ST2: form force and u_act of row r-1; OUT2: also collide f of row r-1
+  // and store it (step) or write the read-out fields (read-out);
+  // ST3: source and g collision of row r-2; PF: prefetch row r+1.
+  // B: prefetch buffer holding row r (row r + 1 goes to the other one).
+  template <bool ST2, bool OUT2, bool ST3, bool PF, int B>
+  __device__ __forceinline__ void iter(int r) {
+    constexpr int E = C::E;
+    float* ah = ph[B];
+    float* ak = pk[B];
     // ---------------- stage 1: row r
     sa = walls && (r < 0 || r >= ny);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      a.h[i] = nh[i];
-      a.k[i] = nk[i];
-    }
-    if (r < r_end) fetch(r + 1);
+    if (PF) fetch<B ^ 1>(min(r + 1, r_end));
+    int fo_off = kDrop;  // outlet memory store of this row
     if (sa) {
-      const float pw = (r < 0 ? D.psiw[0] : D.psiw[1])[xc];
-      a.psi = pw;
-      a.A = D.beta * pw;
-      a.B = pw * pw;
+      const float psiW = r < 0 ? psiS : psiN;
+      a_psi = psiW;
+      a_A = D.beta * psiW;
+      a_B = psiW * psiW;
     } else {
-      const int ry = walls ? r : wrap(r, ny);
+      const int ry = (!EDGE || walls) ? r : wrap1(r, ny);
+      if (EDGE) fix_row(ry, ah, ak, pfo[B]);
       float drho = 0.f, dT = 0.f;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) drho += a.h[i];
-      if (thermal) {
+      for (int i = 0; i < 9; ++i) drho += ah[i];
+      if (TH) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) dT += a.k[i];
+        for (int i = 0; i < 9; ++i) dT += ak[i];
       } else {
         dT = D.T_iso - D.T_ref;
       }
       const float rho = D.rho_ref + drho;
       const float T = D.T_ref + dT;
-      a.drho = drho;
-      a.dT = dT;
-      a.jx = (a.h[1] - a.h[3]) + (a.h[5] - a.h[7]) + (a.h[8] - a.h[6]);
-      a.jy = (a.h[2] - a.h[4]) + (a.h[5] - a.h[7]) + (a.h[6] - a.h[8]);
+      a_drho = drho;
+      a_dT = dT;
+      a_jx = (ah[1] - ah[3]) + (ah[5] - ah[7]) + (ah[8] - ah[6]);
+      a_jy = (ah[2] - ah[4]) + (ah[5] - ah[7]) + (ah[6] - ah[8]);
       float p, psi, dpdT;
       int clamped;
       eos(D, rho, T, p, psi, dpdT, clamped);
-      a.psi = psi;
-      a.A = D.beta * psi;
-      a.B = psi * psi;
-      a.dpdT = dpdT;
-      if (interior && r >= tl.y0 && r < tl.y1) {
-        acc_mass += (double)rho;
-        acc_energy += (double)T;
-        acc_vap += rho < D.rho_mid;
-        acc_clamp += clamped;
-        acc_nf += !(isfinite(rho) && isfinite(T));
-        if (walls && ry == 0 && D.heater[x]) acc_q += 2.0 * (double)(D.Tw[0][x] - T);
-        if (ry == ny / 2) {
-          if (x == 0) acc_pin = (double)p;
-          if (x == nx - 1) acc_pout = (double)p;
+      a_psi = psi;
+      a_A = D.beta * psi;
+      a_B = psi * psi;
+      a_dpdT = dpdT;
+      if (r >= tl.y0 && r < tl.y1) {
+        if (interior) {
+          acc_mass += (double)rho;
+          acc_energy += (double)T;
+          acc_vap += rho < D.rho_mid;
+          acc_clamp += clamped;
+          acc_nf += !(isfinite(rho) && isfinite(T));
         }
-        if (MODE == MODE_STEP && chan && x == nx - 1) {
-          fold_dst[0 * ny + ry] = a.h[3];
-          fold_dst[1 * ny + ry] = a.h[6];
-          fold_dst[2 * ny + ry] = a.h[7];
+        if (EDGE && interior) {
+          if (walls && ry == 0 && heat) acc_q += 2.0 * (double)(twS0 - T);
+          if (ry == ny / 2) {
+            if (x == 0) acc_pin = (double)p;
+            if (x == nx - 1) acc_pout = (double)p;
+          }
+          if (chan && x == nx - 1) fo_off = ry * 4;
         }
       }
+    }
+    if (EDGE && MODE == MODE_STEP) {
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ah[3]), rfd, fo_off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ah[6]), rfd, fo_off, ny * 4, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ah[7]), rfd, fo_off, 2 * ny * 4, 0);
     }
 
     // ---------------- stage 2: row q = r - 1 (b): force, u_act, f collision
     float b_uax = 0.f, b_uay = 0.f, b_irho = 0.f;
-    if (r >= tl.y0 && !sb) {
+    if (ST2 && !sb) {
       float Fx = 0.f, Fy = 0.f;
       if (!D.single_phase) {
-        const float VA = D.G1 * b_A + D.G2 * (a.A + c_A);
-        const float VB = D.G1 * b_B + D.G2 * (a.B + c_B);
-        const float DA = a.A - c_A;
-        const float DB = a.B - c_B;
+        const float VA = D.G1 * b_A + D.G2 * (a_A + c_A);
+        const float VB = D.G1 * b_B + D.G2 * (a_B + c_B);
+        const float DA = a_A - c_A;
+        const float DB = a_B - c_B;
         const float VAr = __shfl_down(VA, 1, kWave), VAl = __shfl_up(VA, 1, kWave);
         const float VBr = __shfl_down(VB, 1, kWave), VBl = __shfl_up(VB, 1, kWave);
         const float DAr = __shfl_down(DA, 1, kWave), DAl = __shfl_up(DA, 1, kWave);
@@ -524,20 +639,20 @@ __device__ void run_tile(const Tile AS4& tl, int gphase) {
       const float ux = b_jx * b_irho, uy = b_jy * b_irho;
       b_uax = ux + 0.5f * Fx * b_irho;
       b_uay = uy + 0.5f * Fy * b_irho;
-      const int q = r - 1;
-      if (MODE == MODE_READOUT) {
-        if (interior && q >= tl.y0 && q < tl.y1) {
-          const long long o = (long long)q * nx + x;
-          D.out[0][o] = rho;
-          D.out[1][o] = b_uax;
-          D.out[2][o] = b_uay;
-          D.out[3][o] = D.T_ref + b_dT;
-        }
-      } else if (q >= tl.y0 && q < tl.y1) {
-        float hs[9];
-        collide_f(D, bh, b_drho, b_jx, b_jy, ux, uy, Fx, Fy, b_irho, hs);
-        if (interior) {
-          const int voff = (q * pitch + x) * E;
+      if (OUT2) {
+        const int q = r - 1;
+        if (MODE == MODE_READOUT) {
+          if (interior) {
+            const long long o = (long long)q * nx + x;
+            D.out[0][o] = rho;
+            D.out[1][o] = b_uax;
+            D.out[2][o] = b_uay;
+            D.out[3][o] = D.T_ref + b_dT;
+          }
+        } else {
+          float hs[9];
+          collide_f(D, bh, b_drho, b_jx, b_jy, ux, uy, Fx, Fy, b_irho, hs);
+          const int voff = interior ? (q * pitch + x) * E : kDrop;
 #pragma unroll
           for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[i], hs[i]);
         }
@@ -545,7 +660,7 @@ __device__ void run_tile(const Tile AS4& tl, int gphase) {
     }
 
     // ---------------- stage 3: row c = r - 2: source and g collision
-    if (MODE == MODE_STEP && thermal && r >= tl.y0 + 2) {
+    if (MODE == MODE_STEP && TH && ST3) {
       const int cr = r - 2;
       float uxl = __shfl_up(c_uax, 1, kWave);
       float uxr = __shfl_down(c_uax, 1, kWave);
@@ -560,11 +675,9 @@ __device__ void run_tile(const Tile AS4& tl, int gphase) {
       const float phi = T * (div_adv - c_dpdT * c_irho * D.inv_cv * div_mass);
       float ks[9];
       collide_g(D, ck, c_dT, T, c_uax, c_uay, phi, ks);
-      if (interior) {
-        const int voff = (cr * pitch + x) * E;
+      const int voff = interior ? (cr * pitch + x) * E : kDrop;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[9 + i], ks[i]);
-      }
+      for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[9 + i], ks[i]);
     }
 
     // ---------------- rotate: d <- c <- b <- a
@@ -573,8 +686,8 @@ __device__ void run_tile(const Tile AS4& tl, int gphase) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       ck[i] = bk[i];
-      bk[i] = a.k[i];
-      bh[i] = a.h[i];
+      bk[i] = ak[i];
+      bh[i] = ah[i];
     }
     c_A = b_A;
     c_B = b_B;
@@ -584,27 +697,96 @@ __device__ void run_tile(const Tile AS4& tl, int gphase) {
     c_uax = b_uax;
     c_uay = b_uay;
     sc = sb;
-    b_drho = a.drho;
-    b_jx = a.jx;
-    b_jy = a.jy;
-    b_dT = a.dT;
-    b_psi = a.psi;
-    b_A = a.A;
-    b_B = a.B;
-    b_dpdT = a.dpdT;
+    b_drho = a_drho;
+    b_jx = a_jx;
+    b_jy = a_jy;
+    b_dT = a_dT;
+    b_psi = a_psi;
+    b_A = a_A;
+    b_B = a_B;
+    b_dpdT = a_dpdT;
     sb = sa;
   }
 
-  // ---- tile partial sums (fixed order: lane tree)
-  double v[kPartials] = {acc_mass, acc_energy, acc_q, (double)acc_vap, (double)acc_clamp,
-                         (double)acc_nf, acc_pin, acc_pout};
+  __device__ __forceinline__ void run() {
+    const int y0 = tl.y0, y1 = tl.y1;
+    fetch<0>(y0 - 2);
+    iter<false, false, false, true, 0>(y0 - 2);
+    iter<false, false, false, true, 1>(y0 - 1);
+    if (MODE == MODE_STEP) {
+      iter<true, false, false, true, 0>(y0);
+      iter<true, true, false, true, 1>(y0 + 1);
+      // steady state: rows y0+2 .. y1, two per trip (buffers 0, 1)
+      int r = y0 + 2;
+      for (; r + 1 <= y1; r += 2) {
+        iter<true, true, true, true, 0>(r);
+        iter<true, true, true, true, 1>(r + 1);
+      }
+      if (r <= y1) {
+        iter<true, true, true, true, 0>(r);
+        iter<true, false, true, false, 1>(y1 + 1);
+      } else {
+        iter<true, false, true, false, 0>(y1 + 1);
+      }
+    } else {
+      iter<true, false, false, true, 0>(y0);
+      int r = y0 + 1;
+      for (; r + 1 < y1; r += 2) {
+        iter<true, true, false, true, 1>(r);
+        iter<true, true, false, true, 0>(r + 1);
+      }
+      if (r < y1) {
+        iter<true, true, false, true, 1>(r);
+        iter<true, true, false, false, 0>(y1);
+      } else {
+        iter<true, true, false, false, 1>(y1);
+      }
+    }
+    // tile partial sums (fixed order: lane tree)
+    double v[kPartials] = {acc_mass, acc_energy, acc_q, (double)acc_vap, (double)acc_clamp,
+                           (double)acc_nf, acc_pin, acc_pout};
 #pragma unroll
-  for (int q = 0; q < kPartials; ++q) v[q] = wave_sum(v[q]);
+    for (int q = 0; q < kPartials; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+      double* out = (MODE == MODE_STEP ? D.partials[phase] : D.readout_partials) + tl.local;
+#pragma unroll
+      for (int q = 0; q < kPartials; ++q) out[(long long)q * D.pstride] = v[q];
+    }
+  }
+};
+
+// Finalizer wave f of a domain: sums slice f of the previous launch's
+// per-tile partials into level-1 slot f.  Wave 0 also records the
+// diagnostics of the state two launches back (whose level-1 slices the
+// previous launch produced) and advances the device step counter.
+__device__ void finalize_slice(const FinEntry AS4& fe, int gphase) {
+  DRef D = *(const DevDomain AS4*)fe.d;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int phase = gphase ^ D.parity;
+  const int f = fe.f;
+  const int T = D.ntiles;
+  const int t0 = (int)((long long)T * f / kFin), t1 = (int)((long long)T * (f + 1) / kFin);
+  double sums[kPartials];
+  sum_partials(D.partials[phase ^ 1], D.pstride, t0, t1, sums);
   if (lane == 0) {
-    double* out = (MODE == MODE_STEP ? D.partials[phase] : D.readout_partials) +
-                  (long long)tl.local * kPartials;
 #pragma unroll
-    for (int q = 0; q < kPartials; ++q) out[q] = v[q];
+    for (int q = 0; q < kPartials; ++q) D.l1[phase ^ 1][f * kPartials + q] = sums[q];
+  }
+  if (f == 0) {
+    double rec[kPartials];
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q)
+      rec[q] = wave_sum(lane < kFin ? D.l1[phase][lane * kPartials + q] : 0.0);
+    if (lane == 0) {
+      const long long st = *D.step_dev;
+      if (st >= 2) {
+        DiagRec& r = D.ring[(st - 2) % kRing];
+        r.step = st - 2;
+#pragma unroll
+        for (int q = 0; q < kPartials; ++q) r.v[q] = rec[q];
+      }
+      *D.step_dev = st + 1;
+    }
   }
 }
 
@@ -617,49 +799,39 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return k * q + min(k, rem) + i;
 }
 
-// Sum of the previous launch's per-tile partials of one domain: lagged mean
-// density for the buoyancy force, the diagnostics record, the step counter.
-__device__ void finalize_domain(DRef D, int gphase) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int phase = gphase ^ D.parity;
-  double sums[kPartials];
-  sum_partials(D.partials[phase ^ 1], D.ntiles, sums);
-  if (lane == 0) {
-    const long long st = *D.step_dev;
-    D.rbar[phase ^ 1] = sums[P_MASS] / ((double)D.nx * (double)D.ny);
-    DiagRec& rec = D.ring[(st + kRing) % kRing];
-    rec.step = st - 1;
-#pragma unroll
-    for (int q = 0; q < kPartials; ++q) rec.v[q] = sums[q];
-    *D.step_dev = st + 1;
-  }
-}
-
-// Blocks [0, kFinalizers) finalize the domains' reductions while the other
-// blocks process tiles; tile blocks keep the XCD of their index (kFinalizers
-// is a multiple of the 8 XCDs).
-constexpr int kFinalizers = 8;
-
 template <int S, int MODE>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void step_kernel(
-    const Tile* __restrict__ tiles, int ntiles, DevDomain* const* __restrict__ doms, int ndoms,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel(
+    const Tile* __restrict__ tiles, int ntiles, const FinEntry* __restrict__ fins, int nfin,
     int gphase) {
-  if (MODE == MODE_STEP && blockIdx.x < kFinalizers) {
-    for (int i = blockIdx.x; i < ndoms; i += kFinalizers)
-      finalize_domain(*(const DevDomain AS4*)((DevDomain* const AS4*)doms)[i], gphase);
+  // Blocks [0, nfin_pad) are finalizer waves (nfin_pad: nfin rounded up to
+  // the 8 XCDs so tile blocks keep the XCD of their index).
+  const int nfin_pad = (nfin + 7) & ~7;
+  if (MODE == MODE_STEP && (int)blockIdx.x < nfin_pad) {
+    if ((int)blockIdx.x < nfin) finalize_slice(((const FinEntry AS4*)fins)[blockIdx.x], gphase);
     return;
   }
-  const int nb = gridDim.x - (MODE == MODE_STEP ? kFinalizers : 0);
-  for (int b = blockIdx.x - (MODE == MODE_STEP ? kFinalizers : 0); b < ntiles; b += nb) {
+  const int skip = MODE == MODE_STEP ? nfin_pad : 0;
+  const int nb = gridDim.x - skip;
+  for (int b = blockIdx.x - skip; b < ntiles; b += nb) {
     const int t = xcd_tile(b, ntiles);
-    run_tile<S, MODE>(((const Tile AS4*)tiles)[t], gphase);
+    const Tile AS4& tl = ((const Tile AS4*)tiles)[t];
+    DRef D = *(const DevDomain AS4*)tl.d;
+    const int r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
+    const bool interior = tl.x0 >= 3 && tl.x0 + kWave - 2 < D.nx && tl.y0 - 2 >= 1 && r_end <= D.ny - 2;
+    if (D.isothermal) {
+      if (interior) TileRun<S, MODE, false, false>(tl, gphase).run();
+      else TileRun<S, MODE, true, false>(tl, gphase).run();
+    } else {
+      if (interior) TileRun<S, MODE, false, true>(tl, gphase).run();
+      else TileRun<S, MODE, true, true>(tl, gphase).run();
+    }
   }
 }
 
 __global__ __launch_bounds__(kWave) void finalize_kernel(const double* __restrict__ parts,
-                                                         int ntiles, double* out) {
+                                                         int stride, int ntiles, double* out) {
   double sums[kPartials];
-  sum_partials(parts, ntiles, sums);
+  sum_partials(parts, stride, 0, ntiles, sums);
   if ((threadIdx.x & (kWave - 1)) == 0)
     for (int q = 0; q < kPartials; ++q) out[q] = sums[q];
 }
@@ -725,12 +897,12 @@ __global__ void copy_kernel(float4* __restrict__ dst, const float4* __restrict__
     default: return hipErrorInvalidValue;                 \
   }
 
-hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, DevDomain* const* doms,
-                           int ndoms, int grid, int phase, hipStream_t s) {
+hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, const FinEntry* fins,
+                           int nfin, int grid, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (grid <= 0 || grid > ntiles) grid = ntiles;
-  grid += kFinalizers;
-#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_STEP>), dim3(grid), dim3(kWave), 0, s, tiles, ntiles, doms, ndoms, phase)
+  grid += (nfin + 7) & ~7;
+#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_STEP>), dim3(grid), dim3(kWave), 0, s, tiles, ntiles, fins, nfin, phase)
   DISPATCH_STORE(storage, L)
 #undef L
   return hipGetLastError();
@@ -738,15 +910,15 @@ hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, DevDomain
 
 hipError_t lbm_launch_readout(int storage, const Tile* tiles, int ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_READOUT>), dim3(ntiles), dim3(kWave), 0, s, tiles, ntiles, (DevDomain* const*)nullptr, 0, phase)
+#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_READOUT>), dim3(ntiles), dim3(kWave), 0, s, tiles, ntiles, (const FinEntry*)nullptr, 0, phase)
   DISPATCH_STORE(storage, L)
 #undef L
   return hipGetLastError();
 }
 
-hipError_t lbm_launch_finalize(DevDomain*, const double* partials, int ntiles, double* out8,
+hipError_t lbm_launch_finalize(const double* partials, int stride, int ntiles, double* out8,
                                hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kWave), 0, s, partials, ntiles, out8);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kWave), 0, s, partials, stride, ntiles, out8);
   return hipGetLastError();
 }
 

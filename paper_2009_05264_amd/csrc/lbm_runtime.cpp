@@ -108,7 +108,7 @@ int validate(const lbm_params* p) {
 namespace {
 
 struct Layout {
-  size_t state, fold, psiw, Tw, heater, partials, rpart, rbar, ring, stepc, out, desc, self, tiles, total;
+  size_t state, fold, psiw, Tw, heater, partials, rpart, l1, rbar, ring, stepc, out, desc, self, tiles, total;
   size_t state_bytes, fold_bytes;
 };
 
@@ -116,7 +116,8 @@ int pitch_of(int nx) { return (nx + 31) / 32 * 32; }
 int elem_bytes(int storage) { return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV ? 2 : 4; }
 int max_tiles(const lbm_params& p) {
   const int strips = (p.nx + kStripInterior - 1) / kStripInterior;
-  return strips * ((p.ny + kMinTileRows - 1) / kMinTileRows);
+  const int t = strips * ((p.ny + kMinTileRows - 1) / kMinTileRows);
+  return (t + 63) / 64 * 64;  // also the stride of the SoA partial sums
 }
 
 Layout layout_of(const lbm_params& p) {
@@ -134,12 +135,13 @@ Layout layout_of(const lbm_params& p) {
   L.heater = o; o += align_up(p.nx * sizeof(int), 256);
   L.partials = o; o += 2 * align_up(mt * kPartials * sizeof(double), 256);
   L.rpart = o; o += align_up(mt * kPartials * sizeof(double), 256);
+  L.l1 = o; o += 2 * align_up(kFin * kPartials * sizeof(double), 256);
   L.rbar = o; o += 256;
   L.ring = o; o += align_up(kRing * sizeof(DiagRec), 256);
   L.stepc = o; o += 256;
   L.out = o; o += 4 * align_up((size_t)p.nx * p.ny * sizeof(float), 256);
   L.desc = o; o += align_up(sizeof(DevDomain), 256);
-  L.self = o; o += 256;
+  L.self = o; o += align_up(kFin * sizeof(FinEntry), 256);
   L.tiles = o; o += align_up(mt * sizeof(Tile), 256);
   L.total = o;
   return L;
@@ -340,6 +342,10 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   D.partials[0] = (double*)(m + L.partials);
   D.partials[1] = (double*)(m + L.partials + pb);
   D.readout_partials = (double*)(m + L.rpart);
+  D.pstride = max_tiles(*p);
+  const size_t l1b = align_up(kFin * kPartials * sizeof(double), 256);
+  D.l1[0] = (double*)(m + L.l1);
+  D.l1[1] = (double*)(m + L.l1 + l1b);
   D.rbar = (double*)(m + L.rbar);
   D.ring = (DiagRec*)(m + L.ring);
   D.step_dev = (long long*)(m + L.stepc);
@@ -347,9 +353,15 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   for (int k = 0; k < 4; ++k) D.out[k] = (float*)(m + L.out + k * ob);
   D.parity = 0;
   d->dev = (DevDomain*)(m + L.desc);
-  d->self_d = (DevDomain**)(m + L.self);
+  d->fins_d = (FinEntry*)(m + L.self);
   d->tiles_d = (Tile*)(m + L.tiles);
-  if (hipMemcpy(d->self_d, &d->dev, sizeof(DevDomain*), hipMemcpyHostToDevice) != hipSuccess) {
+  std::vector<FinEntry> fe(kFin);
+  for (int f = 0; f < kFin; ++f) {
+    fe[f].d = d->dev;
+    fe[f].f = f;
+    fe[f].pad = 0;
+  }
+  if (hipMemcpy(d->fins_d, fe.data(), kFin * sizeof(FinEntry), hipMemcpyHostToDevice) != hipSuccess) {
     lbm_destroy(d);
     return lbm_fail(LBM_E_DEVICE, "descriptor upload failed");
   }
@@ -450,11 +462,14 @@ extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* 
   HIPCHECK(hipMemcpyAsync(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
   HIPCHECK(lbm_launch_init(d->P.storage, d->dev, d->host, rd, td, rho_u, T_u, noise, seed, 0, d->stream));
   // lagged means and the partial sums the first step finalizes
-  const double mean = sum / (double)n;
-  double rb[2] = {mean, mean};
-  HIPCHECK(hipMemcpyAsync(d->host.rbar, rb, sizeof(rb), hipMemcpyHostToDevice, d->stream));
-  std::vector<double> parts((size_t)d->ntiles * kPartials, 0.0);
-  parts[P_MASS] = sum;
+  // pending reductions of the "previous" launches: both level-1 arrays and
+  // the partial sums the first launch's finalizers read hold the initial mass
+  std::vector<double> l1(kFin * kPartials, 0.0);
+  l1[P_MASS] = sum;
+  HIPCHECK(hipMemcpyAsync(d->host.l1[0], l1.data(), l1.size() * sizeof(double), hipMemcpyHostToDevice, d->stream));
+  HIPCHECK(hipMemcpyAsync(d->host.l1[1], l1.data(), l1.size() * sizeof(double), hipMemcpyHostToDevice, d->stream));
+  std::vector<double> parts((size_t)d->host.pstride * kPartials, 0.0);
+  parts[(size_t)P_MASS * d->host.pstride] = sum;
   HIPCHECK(hipMemcpyAsync(d->host.partials[1], parts.data(), parts.size() * sizeof(double),
                           hipMemcpyHostToDevice, d->stream));
   long long zero = 0;
@@ -471,7 +486,7 @@ extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* 
 int lbm_enqueue_steps(lbm_domain* d, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
     const int phase = (int)((d->step + k) & 1) ^ d->host.parity;
-    HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->self_d, 1, d->grid, phase, d->stream));
+    HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->fins_d, kFin, d->grid, phase, d->stream));
   }
   d->step += nsteps;
   return LBM_OK;
@@ -534,7 +549,7 @@ extern "C" int lbm_read_diag(lbm_domain* d, lbm_diag* out) {
   int rc = readout(d);
   if (rc) return rc;
   double* res = (double*)(d->host.rbar) + 16;  // scratch inside the 256-byte rbar block
-  HIPCHECK(lbm_launch_finalize(d->dev, d->host.readout_partials, d->ntiles, res, d->stream));
+  HIPCHECK(lbm_launch_finalize(d->host.readout_partials, d->host.pstride, d->ntiles, res, d->stream));
   double h[kPartials];
   HIPCHECK(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, d->stream));
   HIPCHECK(hipStreamSynchronize(d->stream));
@@ -592,20 +607,22 @@ extern "C" int lbm_save(lbm_domain* d, const char* path) {
   if (!d->inited) return lbm_fail(LBM_E_STATE, "nothing to save");
   const Layout L = layout_of(d->P);
   const int ph = (int)(d->step & 1);
-  const size_t pb = (size_t)d->ntiles * kPartials * sizeof(double);
+  const size_t pb = (size_t)d->host.pstride * kPartials * sizeof(double);
   std::vector<char> st(L.state_bytes), fo(L.fold_bytes), pa(pb);
-  double rb[2];
+  double rb[2 * kFin * kPartials];
   long long sd;
   HIPCHECK(hipStreamSynchronize(d->stream));
   HIPCHECK(hipMemcpy(st.data(), d->host.buf[ph], L.state_bytes, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(fo.data(), d->host.fold[ph], L.fold_bytes, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(pa.data(), d->host.partials[ph ^ 1], pb, hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(rb, d->host.rbar, sizeof(rb), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(rb, d->host.l1[ph], kFin * kPartials * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(rb + kFin * kPartials, d->host.l1[ph ^ 1], kFin * kPartials * sizeof(double),
+                     hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(&sd, d->host.step_dev, sizeof(sd), hipMemcpyDeviceToHost));
   FILE* f = fopen(path, "wb");
   if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s for writing", path);
   CkptHeader h{};
-  memcpy(h.magic, "LBMCKPT1", 8);
+  memcpy(h.magic, "LBMCKPT2", 8);
   h.nx = d->P.nx;
   h.ny = d->P.ny;
   h.storage = d->P.storage;
@@ -627,15 +644,15 @@ extern "C" int lbm_load(lbm_domain* d, const char* path) {
   if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s", path);
   CkptHeader h{};
   const Layout L = layout_of(d->P);
-  const size_t pb = (size_t)d->ntiles * kPartials * sizeof(double);
-  if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "LBMCKPT1", 8) != 0 || h.nx != d->P.nx ||
+  const size_t pb = (size_t)d->host.pstride * kPartials * sizeof(double);
+  if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "LBMCKPT2", 8) != 0 || h.nx != d->P.nx ||
       h.ny != d->P.ny || h.storage != d->P.storage || h.isothermal != d->P.isothermal ||
       h.state_bytes != L.state_bytes || h.fold_bytes != L.fold_bytes || h.part_bytes != pb) {
     fclose(f);
     return lbm_fail(LBM_E_INVALID, "%s does not match this domain (geometry, storage or tiling)", path);
   }
   std::vector<char> st(L.state_bytes), fo(L.fold_bytes), pa(pb);
-  double rb[2];
+  double rb[2 * kFin * kPartials];
   long long sd;
   bool ok = fread(st.data(), 1, st.size(), f) == st.size() && fread(fo.data(), 1, fo.size(), f) == fo.size() &&
             fread(pa.data(), 1, pa.size(), f) == pa.size() && fread(rb, sizeof(rb), 1, f) == 1 &&
@@ -649,7 +666,9 @@ extern "C" int lbm_load(lbm_domain* d, const char* path) {
   HIPCHECK(hipMemcpy(d->host.buf[ph], st.data(), L.state_bytes, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(d->host.fold[ph], fo.data(), L.fold_bytes, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], pa.data(), pb, hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(d->host.rbar, rb, sizeof(rb), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(d->host.l1[ph], rb, kFin * kPartials * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(d->host.l1[ph ^ 1], rb + kFin * kPartials, kFin * kPartials * sizeof(double),
+                     hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(d->host.step_dev, &sd, sizeof(sd), hipMemcpyHostToDevice));
   d->inited = true;
   return LBM_OK;
@@ -729,34 +748,28 @@ extern "C" int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double*
 extern "C" int lbm_set_tile_rows(lbm_domain* d, int rows) {
   if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
   if (rows < 0) return lbm_fail(LBM_E_INVALID, "rows must be >= 0");
-  if (d->inited && d->step > 0) {
-    // the partial sums of the last launch are stored per tile: keep the mass
-    // total by re-finalizing into tile 0 of the new layout
-    const int ph = (int)(d->step & 1);
-    std::vector<double> old((size_t)d->ntiles * kPartials);
+  // The pending partial sums of the last launch are stored per tile: keep
+  // their totals in tile 0 of the new layout (the finalizers' slices of the
+  // new tiling then sum to the same values).
+  const int ph = (int)(d->step & 1);
+  const size_t stride = d->host.pstride;
+  std::vector<double> part(stride * kPartials);
+  if (d->inited) {
     HIPCHECK(hipStreamSynchronize(d->stream));
-    HIPCHECK(hipMemcpy(old.data(), d->host.partials[ph ^ 1], old.size() * sizeof(double), hipMemcpyDeviceToHost));
-    double tot[kPartials] = {0};
-    for (int t = 0; t < d->ntiles; ++t)
-      for (int q = 0; q < kPartials; ++q) tot[q] += old[(size_t)t * kPartials + q];
-    d->rows = rows == 0 ? 0 : std::max(rows, kMinTileRows);
-    int rc = lbm_build_tiles(d);
-    if (rc) return rc;
-    std::vector<double> nw((size_t)d->ntiles * kPartials, 0.0);
-    for (int q = 0; q < kPartials; ++q) nw[q] = tot[q];
-    HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], nw.data(), nw.size() * sizeof(double), hipMemcpyHostToDevice));
-    return LBM_OK;
+    HIPCHECK(hipMemcpy(part.data(), d->host.partials[ph ^ 1], part.size() * sizeof(double),
+                       hipMemcpyDeviceToHost));
   }
+  double tot[kPartials] = {0};
+  for (int q = 0; q < kPartials; ++q)
+    for (int t = 0; t < d->ntiles; ++t) tot[q] += part[(size_t)q * stride + t];
   d->rows = rows == 0 ? 0 : std::max(rows, kMinTileRows);
   int rc = lbm_build_tiles(d);
   if (rc) return rc;
   if (d->inited) {
-    // re-seed the first-step partials for the new tile count
-    double rb[2];
-    HIPCHECK(hipMemcpy(rb, d->host.rbar, sizeof(rb), hipMemcpyDeviceToHost));
-    std::vector<double> parts((size_t)d->ntiles * kPartials, 0.0);
-    parts[P_MASS] = rb[1] * (double)d->P.nx * d->P.ny;
-    HIPCHECK(hipMemcpy(d->host.partials[1], parts.data(), parts.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::fill(part.begin(), part.end(), 0.0);
+    for (int q = 0; q < kPartials; ++q) part[(size_t)q * stride] = tot[q];
+    HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], part.data(), part.size() * sizeof(double),
+                       hipMemcpyHostToDevice));
   }
   return LBM_OK;
 }

@@ -20,7 +20,7 @@ struct lbm_domain {
   lbm_params P{};
   lbm::DevDomain host{};          // host copy of the device descriptor
   lbm::DevDomain* dev = nullptr;  // device descriptor
-  lbm::DevDomain** self_d = nullptr;  // device array holding dev (finalizer list)
+  lbm::FinEntry* fins_d = nullptr;  // this domain's finalizer waves (kFin entries)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   char* mem = nullptr;

@@ -193,7 +193,7 @@ def test_diag_history_records_every_step(L):
     d.step(25)
     h = d.diag_history()
     steps = [r["step"] for r in h]
-    assert steps == list(range(0, 24))  # state n is recorded during step n + 1
+    assert steps == list(range(0, 23))  # state n is recorded during step n + 2
     o = make_oracle(cfg)
     o.init(**cfg.init_args())
     o.step(10)
