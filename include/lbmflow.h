@@ -160,13 +160,16 @@ int lbm_load(lbm_domain* d, const char* path);
 /* Maxwell equal-area coexistence of the Peng-Robinson EOS of p at T < Tc. */
 int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double* rho_v, double* p_sat);
 
-/* Rows per tile of the step kernel (>= 1; 0 restores the default). */
+/* Rows per tile of the step kernel: 0 selects the automatic choice (4 or 8
+ * rows by domain size); values below 2 act as 2.  Results do not depend on
+ * it (bitwise). */
 int lbm_set_tile_rows(lbm_domain* d, int rows);
 
 /* Batched execution: n domains (all created on the same device, stepped
  * together, one launch per step over the concatenated tile table, replayed
- * from a captured hipGraph).  tune_cache_json may be NULL (no autotuning) or
- * a path read/written by the autotuner. */
+ * from a captured hipGraph).  tune_cache_json: NULL = no autotuning (each
+ * domain keeps its own tiles), "" = autotune on the batch without a cache
+ * file, otherwise a text file the autotuner reads and appends to. */
 int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune_cache_json, lbm_batch** out);
 int lbm_batch_step(lbm_batch* b, int64_t nsteps);
 int lbm_batch_sync(lbm_batch* b);

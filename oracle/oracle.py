@@ -98,7 +98,7 @@ def crit_temperature(a=2 / 49, b=2 / 21, R=1.0) -> float:
 @dataclass
 class Params:
     """Model parameters (lattice units).  Defaults: the flow-boiling channel
-    with the readings R1-R31 (tau_f = tau_g = 1, c_v = 6, MRT rates with
+    with the design readings (tau_f = 1, tau_g = 0.6, c_v = 6, MRT rates with
     s_q fixing Lambda = 3/16, g_a = (0, -5e-5))."""
     nx: int = 200
     ny: int = 50

@@ -202,7 +202,7 @@ static std::string batch_key(const lbm_batch* b) {
   std::ostringstream os;
   long long nodes = 0;
   for (lbm_domain* d : b->doms) nodes += (long long)d->P.nx * d->P.ny;
-  os << "n" << b->doms.size() << "_nodes" << nodes;
+  os << "v2_n" << b->doms.size() << "_nodes" << nodes;
   return os.str();
 }
 
@@ -223,7 +223,7 @@ static int autotune(lbm_batch* b, const char* cache) {
       }
     }
   }
-  const int row_opts[] = {16, 32, 64, 128};
+  const int row_opts[] = {4, 6, 8, 12};
   const int grid_opts[] = {0, 8, 16};
   float best = 1e30f;
   int brow = kDefaultTileRows, bgrid = 0;

@@ -303,16 +303,19 @@ __device__ __forceinline__ void sum_partials(const double* parts, int stride, in
 // with compile-time stage flags so that the steady-state iteration is one
 // straight path with a fixed number of loads and stores.
 //
-// EDGE = false: every source of the tile lies inside the domain.  EDGE =
-// true: the same raw-buffer pull with the boundary rules folded into the
-// addresses -- periodic rows wrap in the row offsets; a wall row reads the
-// opposite direction at the node itself (bounce-back) through its plane
-// offsets; lanes of the first / last column correct their x-sources
-// (periodic wrap, or the inlet / outlet sources); the value-level parts of
-// the rules (anti-bounce-back temperatures, Zou-He, convective blend) are
-// applied when the row is consumed.
-template <int S, int MODE, bool EDGE, bool TH>
+// KIND 0 (interior): every source of the tile lies inside the domain.
+// KIND 1 (row edge) and 2 (column edge): the same raw-buffer pull with the
+// boundary rules folded into the addresses -- periodic rows wrap in the row
+// offsets; a wall row reads the opposite direction at the node itself
+// (bounce-back) through its plane offsets; with KIND 2, lanes of the first /
+// last column also correct their x-sources (periodic wrap, or the inlet /
+// outlet sources).  The value-level parts of the rules (anti-bounce-back
+// temperatures, Zou-He, convective blend) are applied when the row is
+// consumed.
+template <int S, int MODE, int KIND, bool TH>
 struct TileRun {
+  static constexpr bool EDGE = KIND != 0;  // rows near a wall or the periodic seam
+  static constexpr bool XE = KIND == 2;    // the tile reaches column 0 or nx - 1
   using C = Codec<S>;
   DRef D;
   const Tile AS4& tl;
@@ -359,18 +362,18 @@ struct TileRun {
     phase = gphase ^ D.parity;
     nx = D.nx;
     ny = D.ny;
-    chan = EDGE && D.bc_x == LBM_BCX_CHANNEL;
+    chan = XE && D.bc_x == LBM_BCX_CHANNEL;
     walls = EDGE && D.bc_y == LBM_BCY_WALLS;
     fold = D.fold[phase];
     fold_dst = D.fold[phase ^ 1];
     x = tl.x0 - 2 + lane;
-    xc = !EDGE ? x : (chan ? clampi(x, 0, nx - 1) : wrap(x, nx));
+    xc = !XE ? x : (chan ? clampi(x, 0, nx - 1) : wrap(x, nx));
     interior = lane >= 2 && lane < kWave - 2 && x < nx;
     xlo = chan && x == 0;
     xhi = chan && x == nx - 1;
     has_out = chan && tl.x0 + kWave - 3 >= nx - 1;
-    mL = EDGE && xc == 0 ? -1 : 0;
-    mR = EDGE && xc == nx - 1 ? -1 : 0;
+    mL = XE && xc == 0 ? -1 : 0;
+    mR = XE && xc == nx - 1 ? -1 : 0;
     pitch = D.pitch;
     constexpr int E = C::E;
     const int plane = (int)D.plane;
@@ -392,8 +395,10 @@ struct TileRun {
       // Every load and store of a boundary tile is issued unconditionally
       // (offset kDrop where it has nothing to move), so that the march keeps
       // a fixed count of memory operations per row.
-      rfo = make_rsrc(fold);
-      rfd = make_rsrc(fold_dst);
+      if (XE) {
+        rfo = make_rsrc(fold);
+        rfd = make_rsrc(fold_dst);
+      }
       const bool needS = walls && tl.y0 - 2 <= 0, needN = walls && r_end >= ny - 1;
       const int xm = chan ? max(xc - 1, 0) : (xc == 0 ? nx - 1 : xc - 1);
       const int xp = chan ? min(xc + 1, nx - 1) : (xc == nx - 1 ? 0 : xc + 1);
@@ -441,7 +446,6 @@ struct TileRun {
       const int R0 = (rsr + 1) * PE, R1 = (ro + 1) * PE, R2 = (rnr + 1) * PE;
       const int xe = xc * E;
       const int vr[3] = {solid ? kDrop : xe + R0, solid ? kDrop : xe + R1, solid ? kDrop : xe + R2};
-      const int mLr = solid ? 0 : mL, mRr = solid ? 0 : mR;
 #pragma unroll
       for (int i = 0; i < 9; ++i) vf[i] = vg[i] = vr[1 - CY[i]];
       // bounce-back sources: the opposite direction at the node itself
@@ -461,48 +465,51 @@ struct TileRun {
         so[16] = sst[14] - E;
         so[17] = sst[15] + E;
       }
-      const int P = sst[1];
-      int cL1, cL5, cL8, gL1, gL5, gL8, cR3, cR6, cR7;
-      if (chan) {
-        // inlet column: the f slots of 1, 5, 8 (replaced by Zou-He) carry g
-        // of 3, 7, 6 at the node itself for the anti-bounce-back rule; the g
-        // slots keep their in-buffer ghost source.  Outlet column: the
-        // sources of 3, 6, 7 move from column nx to column nx-1.
-        cL1 = TH ? 11 * P + E : 0;
-        cL5 = (TH && !wS) ? 11 * P + E + (R1 - R0) : 0;
-        cL8 = (TH && !wN) ? 7 * P + E + (R1 - R2) : 0;
-        gL1 = gL5 = gL8 = 0;
-        cR3 = -E;
-        cR6 = wS ? 0 : -E;
-        cR7 = wN ? 0 : -E;
-      } else {
-        const int W = nx * E;
-        cL1 = W;
-        cL5 = wS ? 0 : W;
-        cL8 = wN ? 0 : W;
-        gL1 = cL1;
-        gL5 = cL5;
-        gL8 = cL8;
-        cR3 = -W;
-        cR6 = wS ? 0 : -W;
-        cR7 = wN ? 0 : -W;
+      if (XE) {
+        const int mLr = solid ? 0 : mL, mRr = solid ? 0 : mR;
+        const int P = sst[1];
+        int cL1, cL5, cL8, gL1, gL5, gL8, cR3, cR6, cR7;
+        if (chan) {
+          // inlet column: the f slots of 1, 5, 8 (replaced by Zou-He) carry g
+          // of 3, 7, 6 at the node itself for the anti-bounce-back rule; the g
+          // slots keep their in-buffer ghost source.  Outlet column: the
+          // sources of 3, 6, 7 move from column nx to column nx-1.
+          cL1 = TH ? 11 * P + E : 0;
+          cL5 = (TH && !wS) ? 11 * P + E + (R1 - R0) : 0;
+          cL8 = (TH && !wN) ? 7 * P + E + (R1 - R2) : 0;
+          gL1 = gL5 = gL8 = 0;
+          cR3 = -E;
+          cR6 = wS ? 0 : -E;
+          cR7 = wN ? 0 : -E;
+        } else {
+          const int W = nx * E;
+          cL1 = W;
+          cL5 = wS ? 0 : W;
+          cL8 = wN ? 0 : W;
+          gL1 = cL1;
+          gL5 = cL5;
+          gL8 = cL8;
+          cR3 = -W;
+          cR6 = wS ? 0 : -W;
+          cR7 = wN ? 0 : -W;
+        }
+        vf[1] += mLr & cL1;
+        vf[5] += mLr & cL5;
+        vf[8] += mLr & cL8;
+        vg[1] += mLr & gL1;
+        vg[5] += mLr & gL5;
+        vg[8] += mLr & gL8;
+        vf[3] += mRr & cR3;
+        vf[6] += mRr & cR6;
+        vf[7] += mRr & cR7;
+        vg[3] += mRr & cR3;
+        vg[6] += mRr & cR6;
+        vg[7] += mRr & cR7;
+        const int vo = has_out && !solid ? ro * 4 : kDrop;
+        pfo[B][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 0, 0));
+        pfo[B][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, ny * 4, 0));
+        pfo[B][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 2 * ny * 4, 0));
       }
-      vf[1] += mLr & cL1;
-      vf[5] += mLr & cL5;
-      vf[8] += mLr & cL8;
-      vg[1] += mLr & gL1;
-      vg[5] += mLr & gL5;
-      vg[8] += mLr & gL8;
-      vf[3] += mRr & cR3;
-      vf[6] += mRr & cR6;
-      vf[7] += mRr & cR7;
-      vg[3] += mRr & cR3;
-      vg[6] += mRr & cR6;
-      vg[7] += mRr & cR7;
-      const int vo = has_out && !solid ? ro * 4 : kDrop;
-      pfo[B][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 0, 0));
-      pfo[B][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, ny * 4, 0));
-      pfo[B][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 2 * ny * 4, 0));
     }
     pull_dirs<S, TH>(rs, vf, vg, so, ph[B], pk[B]);
   }
@@ -606,7 +613,7 @@ struct TileRun {
         }
       }
     }
-    if (EDGE && MODE == MODE_STEP) {
+    if (XE && MODE == MODE_STEP) {
       __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ah[3]), rfd, fo_off, 0, 0);
       __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ah[6]), rfd, fo_off, ny * 4, 0);
       __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ah[7]), rfd, fo_off, 2 * ny * 4, 0);
@@ -817,13 +824,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     const Tile AS4& tl = ((const Tile AS4*)tiles)[t];
     DRef D = *(const DevDomain AS4*)tl.d;
     const int r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
-    const bool interior = tl.x0 >= 3 && tl.x0 + kWave - 2 < D.nx && tl.y0 - 2 >= 1 && r_end <= D.ny - 2;
+    const bool xin = tl.x0 >= 3 && tl.x0 + kWave - 2 < D.nx;
+    const bool yin = tl.y0 - 2 >= 1 && r_end <= D.ny - 2;
     if (D.isothermal) {
-      if (interior) TileRun<S, MODE, false, false>(tl, gphase).run();
-      else TileRun<S, MODE, true, false>(tl, gphase).run();
+      if (!xin) TileRun<S, MODE, 2, false>(tl, gphase).run();
+      else if (!yin) TileRun<S, MODE, 1, false>(tl, gphase).run();
+      else TileRun<S, MODE, 0, false>(tl, gphase).run();
     } else {
-      if (interior) TileRun<S, MODE, false, true>(tl, gphase).run();
-      else TileRun<S, MODE, true, true>(tl, gphase).run();
+      if (!xin) TileRun<S, MODE, 2, true>(tl, gphase).run();
+      else if (!yin) TileRun<S, MODE, 1, true>(tl, gphase).run();
+      else TileRun<S, MODE, 0, true>(tl, gphase).run();
     }
   }
 }

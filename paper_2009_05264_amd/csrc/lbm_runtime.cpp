@@ -116,7 +116,7 @@ int pitch_of(int nx) { return (nx + 31) / 32 * 32; }
 int elem_bytes(int storage) { return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV ? 2 : 4; }
 int max_tiles(const lbm_params& p) {
   const int strips = (p.nx + kStripInterior - 1) / kStripInterior;
-  const int t = strips * ((p.ny + kMinTileRows - 1) / kMinTileRows);
+  const int t = strips * ((p.ny + kMinTileRows - 1) / kMinTileRows + 2);
   return (t + 63) / 64 * 64;  // also the stride of the SoA partial sums
 }
 
@@ -244,14 +244,41 @@ void fill_desc(lbm_domain* d) {
 
 }  // namespace
 
-// Rows per tile: the requested value, or (auto) enough tiles to give every
-// SIMD of the 256 CUs about three waves, between 4 and 64 rows.
+// Rows per tile (automatic).  A tile's march spends four extra row steps
+// filling its pipeline, so short tiles trade redundant pulls for
+// parallelism: domains of up to about 4k four-row tiles use 4 rows (every
+// SIMD of the 256 CUs gets work), larger ones 8 rows (pull overhead 1.5x,
+// still several waves per SIMD).
 int lbm_auto_rows(int nx, int ny) {
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
-  const long long want = 3072;
-  int rows = (int)((strips * (long long)ny + want - 1) / want);
-  rows = (rows + 3) / 4 * 4;
-  return std::min(64, std::max(kMinTileRows, rows));
+  return (long long)strips * ((ny + 3) / 4) <= 4096 ? 4 : 8;
+}
+
+// Row segments [y0, y1) of one strip.  Tiles that run the boundary path do
+// more work per row, so they get fewer rows: strips that reach column 0 or
+// nx - 1 are cut in chunks of rows / 2; the other strips get a 3-row head
+// and tail (the rows within two of a wall or of the periodic seam) and
+// near-equal chunks of about `rows` in between.
+static void strip_segments(int ny, int rows, bool column_edge, std::vector<std::pair<int, int>>& seg) {
+  seg.clear();
+  if (column_edge) {
+    const int re = std::max(kMinTileRows, rows / 2);
+    for (int y = 0; y < ny; y += re) seg.push_back({y, std::min(ny, y + re)});
+    return;
+  }
+  const int h = std::min(3, ny), t = std::min(3, ny - h);
+  seg.push_back({0, h});
+  const int len = ny - h - t;
+  if (len > 0) {
+    const int nb = (len + rows - 1) / rows;
+    int y = h;
+    for (int k = 0; k < nb; ++k) {
+      const int n = len / nb + (k < len % nb ? 1 : 0);
+      seg.push_back({y, y + n});
+      y += n;
+    }
+  }
+  if (t > 0) seg.push_back({ny - t, ny});
 }
 
 int lbm_build_tiles(lbm_domain* d) {
@@ -259,18 +286,32 @@ int lbm_build_tiles(lbm_domain* d) {
   const int nx = d->P.nx, ny = d->P.ny;
   const int rows = d->rows > 0 ? std::max(kMinTileRows, d->rows) : lbm_auto_rows(nx, ny);
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
-  const int segs = (ny + rows - 1) / rows;
   d->tiles_h.clear();
-  for (int s = 0; s < segs; ++s)
-    for (int t = 0; t < strips; ++t) {
+  std::vector<std::pair<int, int>> seg;
+  for (int t = 0; t < strips; ++t) {
+    const int x0 = t * kStripInterior;
+    // same test as the kernel's choice of the column-edge path
+    const bool column_edge = !(x0 >= 3 && x0 + kWave - 2 < nx);
+    strip_segments(ny, rows, column_edge, seg);
+    for (const auto& sg : seg) {
       Tile tl;
       tl.d = d->dev;
-      tl.x0 = t * kStripInterior;
-      tl.y0 = s * rows;
-      tl.y1 = std::min(ny, tl.y0 + rows);
-      tl.local = (int)d->tiles_h.size();
+      tl.x0 = x0;
+      tl.y0 = sg.first;
+      tl.y1 = sg.second;
       d->tiles_h.push_back(tl);
     }
+  }
+  // Row-major launch order: the tiles in flight at any time cover a few
+  // full-width row bands, so every plane is streamed in long contiguous
+  // runs (DRAM pages, TLB reach) rather than in narrow vertical bands.
+  std::stable_sort(d->tiles_h.begin(), d->tiles_h.end(), [](const Tile& a, const Tile& b) {
+    return a.y0 != b.y0 ? a.y0 < b.y0 : a.x0 < b.x0;
+  });
+  for (size_t i = 0; i < d->tiles_h.size(); ++i) d->tiles_h[i].local = (int)i;
+  if ((int)d->tiles_h.size() > d->host.pstride)
+    return lbm_fail(LBM_E_CAP, "tile table of %zu tiles exceeds its capacity %d", d->tiles_h.size(),
+                    d->host.pstride);
   d->ntiles = (int)d->tiles_h.size();
   d->host.ntiles = d->ntiles;
   HIPCHECK(hipMemcpyAsync(d->tiles_d, d->tiles_h.data(), d->ntiles * sizeof(Tile),

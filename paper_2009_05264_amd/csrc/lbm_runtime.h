@@ -8,8 +8,8 @@
 #include "../../include/lbmflow.h"
 #include "lbm_internal.h"
 
-constexpr int kMinTileRows = 4;
-constexpr int kDefaultTileRows = 32;
+constexpr int kMinTileRows = 2;
+constexpr int kDefaultTileRows = 8;
 
 struct GraphEntry {
   hipGraph_t graph = nullptr;
