@@ -175,6 +175,80 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps);
 int lbm_batch_sync(lbm_batch* b);
 int lbm_batch_destroy(lbm_batch* b);
 
+/* ---------------------------------------------------------------- serving
+ * A server owns a queue of flow-boiling solves.  lbm_server_submit records a
+ * request (parameters, wall maps and initial state are copied) with its
+ * arrival time.  Each lbm_server_pump call
+ *   1. admits queued requests in arrival order while their device footprint
+ *      (lbm_required_bytes) fits under the cap next to the resident ones and
+ *      a slot is free (a request that does not fit is passed over, not
+ *      blocking smaller ones behind it), creating and initialising each
+ *      domain on the server's stream;
+ *   2. steps every running request together, one launch per step over all
+ *      their tiles (lbm_batch_*), for min(quantum, smallest remaining
+ *      budget) steps, and waits for them;
+ *   3. retires the requests whose budget is reached (time to solution =
+ *      completion minus arrival, host steady clock).
+ * Results of a finished request stay resident (and count against the cap)
+ * until lbm_server_release.  A request's result does not depend on what it
+ * was batched with: each domain keeps its own tiles and reductions.
+ * The server is used by one host thread at a time.                         */
+typedef struct lbm_server lbm_server;
+
+/* Boundary maps and initial state of one request (arrays of nx entries,
+ * copied at submit).  Wall maps are required when bc_y == LBM_BCY_WALLS;
+ * heater may be NULL. */
+typedef struct {
+  const double* T_wall_s;
+  const double* rho_w_s;
+  const int32_t* heater;
+  const double* T_wall_n;
+  const double* rho_w_n;
+  double rho_init, T_init, noise; /* lbm_init_fields(rho_uniform, T_uniform, noise_rel) */
+  uint64_t seed;
+} lbm_request;
+
+enum { LBM_REQ_QUEUED = 0, LBM_REQ_RUNNING = 1, LBM_REQ_DONE = 2, LBM_REQ_CANCELLED = 3,
+       LBM_REQ_FAILED = 4 };
+
+typedef struct {
+  int64_t queued, running, done;
+  size_t resident_bytes, peak_resident_bytes;
+  double lups;          /* lattice updates completed by the server        */
+  double busy_seconds;  /* host time spent inside device quanta           */
+} lbm_server_info;
+
+/* hbm_cap_bytes > 0: bound on the summed footprint of resident requests;
+ * max_slots > 0: bound on running requests; quantum_steps > 0: steps between
+ * admission points.  hip_stream as for lbm_create. */
+int lbm_server_create(size_t hbm_cap_bytes, int max_slots, int64_t quantum_steps, void* hip_stream,
+                      lbm_server** out);
+/* LBM_E_CAP if the request alone exceeds the cap (it is not queued). */
+int lbm_server_submit(lbm_server* s, const lbm_params* p, const lbm_request* r, int64_t step_budget,
+                      uint64_t* req_id);
+/* One admission + quantum + retirement round; *running (may be NULL)
+ * receives the number of requests still running. */
+int lbm_server_pump(lbm_server* s, int* running);
+/* *state = LBM_REQ_*; *time_to_solution_s (may be NULL) = completion minus
+ * arrival in seconds once done, else -1. */
+int lbm_server_poll(lbm_server* s, uint64_t req_id, int* state, double* time_to_solution_s);
+/* Fields / diagnostics of a finished request (as lbm_read_fields/_diag). */
+int lbm_server_read_fields(lbm_server* s, uint64_t req_id, double* rho, double* ux, double* uy,
+                           double* T);
+int lbm_server_read_diag(lbm_server* s, uint64_t req_id, lbm_diag* out);
+/* Free the device state of a finished request. */
+int lbm_server_release(lbm_server* s, uint64_t req_id);
+/* Drop a queued or running request (its device state is freed). */
+int lbm_server_cancel(lbm_server* s, uint64_t req_id);
+int lbm_server_stats(lbm_server* s, lbm_server_info* out);
+int lbm_server_destroy(lbm_server* s);
+
+/* The server's admission rule on its own (host only): scan footprints[0..n)
+ * in order, admitting each that fits in cap - used while free_slots remain;
+ * admit[0..*n_admit) receives the admitted indices. */
+int lbm_admission_plan(const size_t* footprints, int n, size_t cap, size_t used, int free_slots,
+                       int* admit, int* n_admit);
+
 /* Plain device copy of bytes (HBM copy ceiling and counter calibration). */
 int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 

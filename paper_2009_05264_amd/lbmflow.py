@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbmflow.so")
 
 LBM_OK = 0
+LBM_E_INVALID, LBM_E_NOMEM, LBM_E_CAP, LBM_E_DEVICE, LBM_E_NAN, LBM_E_STATE = -1, -2, -3, -4, -5, -6
 STORE_F32, STORE_F32_DEV, STORE_F16_DEV, STORE_BF16_DEV = 0, 1, 2, 3
 BCX_PERIODIC, BCX_CHANNEL = 0, 1
 BCY_PERIODIC, BCY_WALLS = 0, 1
@@ -45,6 +46,24 @@ class Diag(C.Structure):
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
+
+class Request(C.Structure):
+    _fields_ = [("T_wall_s", C.POINTER(C.c_double)), ("rho_w_s", C.POINTER(C.c_double)),
+                ("heater", C.POINTER(C.c_int32)), ("T_wall_n", C.POINTER(C.c_double)),
+                ("rho_w_n", C.POINTER(C.c_double)), ("rho_init", C.c_double), ("T_init", C.c_double),
+                ("noise", C.c_double), ("seed", C.c_uint64)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("running", C.c_int64), ("done", C.c_int64),
+                ("resident_bytes", C.c_size_t), ("peak_resident_bytes", C.c_size_t),
+                ("lups", C.c_double), ("busy_seconds", C.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
 
 _lib = None
 
@@ -81,6 +100,19 @@ def lib():
             "lbm_batch_sync": (C.c_int, [vp]),
             "lbm_batch_destroy": (C.c_int, [vp]),
             "lbm_stream_copy": (C.c_int, [vp, vp, C.c_size_t, vp]),
+            "lbm_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_int64, vp, C.POINTER(vp)]),
+            "lbm_server_submit": (C.c_int, [vp, C.POINTER(Params), C.POINTER(Request), C.c_int64,
+                                            C.POINTER(C.c_uint64)]),
+            "lbm_server_pump": (C.c_int, [vp, C.POINTER(C.c_int)]),
+            "lbm_server_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int), dp]),
+            "lbm_server_read_fields": (C.c_int, [vp, C.c_uint64, dp, dp, dp, dp]),
+            "lbm_server_read_diag": (C.c_int, [vp, C.c_uint64, C.POINTER(Diag)]),
+            "lbm_server_release": (C.c_int, [vp, C.c_uint64]),
+            "lbm_server_cancel": (C.c_int, [vp, C.c_uint64]),
+            "lbm_server_stats": (C.c_int, [vp, C.POINTER(ServerInfo)]),
+            "lbm_server_destroy": (C.c_int, [vp]),
+            "lbm_admission_plan": (C.c_int, [C.POINTER(C.c_size_t), C.c_int, C.c_size_t, C.c_size_t,
+                                             C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -230,6 +262,88 @@ class Batch:
     def close(self):
         if getattr(self, "h", None) and self.h.value:
             lib().lbm_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def admission_plan(footprints, cap: int, used: int, free_slots: int) -> list:
+    """The server's admission rule (host only): indices admitted in order."""
+    n = len(footprints)
+    fp = (C.c_size_t * max(n, 1))(*[int(f) for f in footprints])
+    adm = (C.c_int * max(n, 1))()
+    na = C.c_int()
+    _check(lib().lbm_admission_plan(fp, n, int(cap), int(used), int(free_slots), adm, C.byref(na)))
+    return [adm[i] for i in range(na.value)]
+
+
+class Server:
+    """Continuous-batching server of flow-boiling solves (lbm_server_*)."""
+
+    def __init__(self, cap_bytes: int, max_slots: int = 256, quantum: int = 500, stream: int | None = None):
+        h = C.c_void_p()
+        _check(lib().lbm_server_create(int(cap_bytes), int(max_slots), int(quantum), C.c_void_p(stream or 0),
+                                       C.byref(h)))
+        self.h = h
+
+    def submit(self, params: Params, budget: int, walls=None, rho_init=1.0, T_init=1.0, noise=0.0,
+               seed=0) -> int:
+        """walls: (T_south, rho_w_south, heater, T_north, rho_w_north), each [nx] (heater may be None)."""
+        r = Request()
+        keep = []
+        if walls is not None:
+            Ts, rws, heat, Tn, rwn = walls
+            arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, float), (params.nx,)))
+                    for a in (Ts, rws, Tn, rwn)]
+            keep += arrs
+            r.T_wall_s, r.rho_w_s, r.T_wall_n, r.rho_w_n = [_dp(a) for a in arrs]
+            if heat is not None:
+                ha = np.ascontiguousarray(np.asarray(heat, dtype=np.int32))
+                keep.append(ha)
+                r.heater = ha.ctypes.data_as(C.POINTER(C.c_int32))
+        r.rho_init, r.T_init, r.noise, r.seed = float(rho_init), float(T_init), float(noise), int(seed)
+        rid = C.c_uint64()
+        _check(lib().lbm_server_submit(self.h, C.byref(params), C.byref(r), int(budget), C.byref(rid)))
+        return rid.value
+
+    def pump(self) -> int:
+        n = C.c_int()
+        _check(lib().lbm_server_pump(self.h, C.byref(n)))
+        return n.value
+
+    def poll(self, rid: int):
+        st, t = C.c_int(), C.c_double()
+        _check(lib().lbm_server_poll(self.h, rid, C.byref(st), C.byref(t)))
+        return st.value, t.value
+
+    def fields(self, rid: int, nx: int, ny: int) -> dict:
+        out = {k: np.zeros((ny, nx)) for k in ("rho", "ux", "uy", "T")}
+        _check(lib().lbm_server_read_fields(self.h, rid, *[_dp(out[k]) for k in ("rho", "ux", "uy", "T")]))
+        return out
+
+    def diag(self, rid: int) -> dict:
+        d = Diag()
+        _check(lib().lbm_server_read_diag(self.h, rid, C.byref(d)))
+        return d.as_dict()
+
+    def release(self, rid: int):
+        _check(lib().lbm_server_release(self.h, rid))
+
+    def cancel(self, rid: int):
+        _check(lib().lbm_server_cancel(self.h, rid))
+
+    def stats(self) -> dict:
+        s = ServerInfo()
+        _check(lib().lbm_server_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().lbm_server_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):

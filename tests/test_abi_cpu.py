@@ -68,3 +68,52 @@ def test_ensemble_is_seeded():
     a, b = W.ensemble(), W.ensemble()
     assert [(c.nx, c.ny, c.u_in) for c in a] == [(c.nx, c.ny, c.u_in) for c in b]
     assert len(a) == 64 and {c.nx for c in a} <= {400, 800, 1200, 1600} and {c.ny for c in a} <= {50, 100, 200}
+
+
+def test_server_structs_match_header():
+    from paper_2009_05264_amd import lbmflow as L
+
+    assert C.sizeof(L.Request) == 5 * 8 + 3 * 8 + 8
+    assert C.sizeof(L.ServerInfo) == 3 * 8 + 2 * 8 + 2 * 8
+    txt = open(HEADER).read()
+    for st in ("LBM_REQ_QUEUED = 0", "LBM_REQ_RUNNING = 1", "LBM_REQ_DONE = 2", "LBM_REQ_CANCELLED = 3",
+               "LBM_REQ_FAILED = 4"):
+        assert st in txt, st
+
+
+def test_admission_in_arrival_order_by_footprint():
+    """First fit in arrival order: a request that does not fit is passed
+    over without blocking smaller ones behind it; slots bound the count."""
+    from paper_2009_05264_amd import lbmflow as L
+
+    assert L.admission_plan([5, 3, 8, 1, 2], cap=10, used=0, free_slots=3) == [0, 1, 3]
+    assert L.admission_plan([5, 3, 8, 1, 2], cap=10, used=0, free_slots=10) == [0, 1, 3]
+    assert L.admission_plan([5, 3, 8, 1, 2], cap=10, used=4, free_slots=10) == [0, 3]
+    assert L.admission_plan([10], cap=10, used=0, free_slots=1) == [0]  # exact fit
+    assert L.admission_plan([1, 1], cap=10, used=11, free_slots=5) == []  # already over the cap
+    assert L.admission_plan([1, 1, 1], cap=10, used=0, free_slots=0) == []
+    assert L.admission_plan([], cap=10, used=0, free_slots=3) == []
+    # never exceeds the cap, whatever the order
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        fp = rng.integers(1, 50, size=20)
+        cap, used = 100, int(rng.integers(0, 60))
+        adm = L.admission_plan(list(fp), cap=cap, used=used, free_slots=int(rng.integers(0, 20)))
+        assert used + sum(fp[i] for i in adm) <= cap
+        assert adm == sorted(adm)
+        # every passed-over request before the last admitted one did not fit at its turn
+        tot = used
+        for i in range(max(adm) + 1 if adm else 0):
+            if i in adm:
+                tot += fp[i]
+            else:
+                assert tot + fp[i] > cap
+
+
+def test_admission_plan_rejects_bad_arguments():
+    from paper_2009_05264_amd import lbmflow as L
+
+    lib = L.lib()
+    na = C.c_int()
+    assert lib.lbm_admission_plan(None, -1, 10, 0, 1, None, C.byref(na)) == L.LBM_E_INVALID
+    assert lib.lbm_admission_plan(None, 2, 10, 0, 1, None, C.byref(na)) == L.LBM_E_INVALID

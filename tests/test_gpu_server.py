@@ -1,0 +1,134 @@
+"""GPU tests of the serving loop (lbm_server_*): requests of different sizes,
+parameters and storage kinds arrive while others run, are admitted under a
+memory cap, and each result equals the same solve run alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_05264_amd import lbmflow
+
+    lbmflow.lib()
+    return lbmflow
+
+
+def request_set():
+    """Ten small flow-boiling channels with different sizes, inlet speeds,
+    superheats, wettabilities, seeds, storage kinds and step budgets."""
+    rng = np.random.default_rng(11)
+    sizes = [(130, 40), (200, 50), (250, 30), (190, 64), (67, 13)]
+    out = []
+    for i in range(10):
+        nx, ny = sizes[i % len(sizes)]
+        cfg = W.Channel(nx=nx, ny=ny, u_in=float(rng.uniform(0.002, 0.01)),
+                        superheat=float(rng.uniform(0.05, 0.2)), heater_len=max(2, int(0.4 * ny)),
+                        rho_w=float(rng.uniform(3.0, 4.6)), seed=100 + i)
+        storage = "F16_DEV" if i % 3 == 2 else "F32_DEV"
+        budget = int(rng.choice([60, 100, 140, 200]))
+        out.append((cfg, storage, budget))
+    return out
+
+
+def params_of(L, cfg, storage):
+    return L.default_params(storage=getattr(L, "STORE_" + storage), rho_ref=W.RHO_L, T_ref=cfg.T_sat,
+                            **cfg.params())
+
+
+def run_alone(L, cfg, storage, budget):
+    d = L.Domain(params_of(L, cfg, storage))
+    Ts, rws, heat, Tn, rwn = cfg.walls()
+    d.set_wall(L.SIDE_S, Ts, rws, heat)
+    d.set_wall(L.SIDE_N, Tn, rwn)
+    d.init(**cfg.init_args())
+    d.step(budget)
+    f, g = d.fields(), d.diag()
+    d.close()
+    return f, g
+
+
+def submit(L, srv, cfg, storage, budget):
+    ia = cfg.init_args()
+    return srv.submit(params_of(L, cfg, storage), budget, walls=cfg.walls(), rho_init=ia["rho_u"],
+                      T_init=ia["T_u"], noise=ia["noise"], seed=ia["seed"])
+
+
+def test_results_equal_alone_and_in_the_mix(L):
+    reqs = request_set()
+    fps = [L.required_bytes(params_of(L, c, s)) for c, s, _ in reqs]
+    cap = sum(sorted(fps)[-4:])  # about four resident at a time: later arrivals queue
+    srv = L.Server(cap, max_slots=6, quantum=40)
+    print(f"case: server cap={cap} requests={len(reqs)}", flush=True)
+    ids = {}
+    # half arrive up front, the rest one per quantum while the first ones run
+    for k in range(5):
+        ids[submit(L, srv, *reqs[k])] = k
+    pending = list(range(5, len(reqs)))
+    results, tts = {}, {}
+    for _ in range(1000):
+        if pending:
+            k = pending.pop(0)
+            ids[submit(L, srv, *reqs[k])] = k
+        running = srv.pump()
+        for rid, k in list(ids.items()):
+            st, t = srv.poll(rid)
+            assert st != L.REQ_FAILED
+            if st == L.REQ_DONE and k not in results:
+                cfg = reqs[k][0]
+                results[k] = (srv.fields(rid, cfg.nx, cfg.ny), srv.diag(rid))
+                tts[k] = t
+                srv.release(rid)
+        info = srv.stats()
+        assert info["peak_resident_bytes"] <= cap
+        if not pending and running == 0 and info["queued"] == 0:
+            break
+    info = srv.stats()
+    srv.close()
+    assert len(results) == len(reqs), (len(results), info)
+    assert info["resident_bytes"] == 0 and info["done"] == len(reqs)
+    assert info["lups"] == pytest.approx(sum(c.nx * c.ny * b for c, _, b in reqs))
+    for k, (cfg, storage, budget) in enumerate(reqs):
+        f_mix, d_mix = results[k]
+        f_alone, d_alone = run_alone(L, cfg, storage, budget)
+        for key in f_alone:
+            assert np.array_equal(f_mix[key], f_alone[key]), (k, key)
+        assert d_mix["step"] == budget and d_mix["mass"] == d_alone["mass"], k
+        assert tts[k] > 0
+
+
+def test_cancel_and_cap(L):
+    cfg, storage, _ = request_set()[1]
+    fp = L.required_bytes(params_of(L, cfg, storage))
+    srv = L.Server(fp, max_slots=4, quantum=20)  # room for one at a time
+    print("case: server cancel", flush=True)
+    a = submit(L, srv, cfg, storage, 100)
+    b = submit(L, srv, cfg, storage, 100)
+    c = submit(L, srv, cfg, storage, 40)
+    srv.pump()
+    assert srv.poll(a)[0] == L.REQ_RUNNING and srv.poll(b)[0] == L.REQ_QUEUED
+    srv.cancel(b)
+    srv.cancel(a)
+    assert srv.poll(a)[0] == L.REQ_CANCELLED and srv.poll(b)[0] == L.REQ_CANCELLED
+    for _ in range(10):
+        if srv.pump() == 0 and srv.stats()["queued"] == 0:
+            break
+    assert srv.poll(c)[0] == L.REQ_DONE
+    f = srv.fields(c, cfg.nx, cfg.ny)
+    f_alone, _ = run_alone(L, cfg, storage, 40)
+    assert np.array_equal(f["rho"], f_alone["rho"])
+    srv.release(c)
+    assert srv.stats()["resident_bytes"] == 0
+    # a request larger than the cap is refused, not queued
+    big = W.Channel(nx=cfg.nx * 4, ny=cfg.ny)
+    with pytest.raises(L.LbmError) as e:
+        submit(L, srv, big, storage, 10)
+    assert e.value.code == L.LBM_E_CAP
+    srv.close()
