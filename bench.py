@@ -189,6 +189,27 @@ def main():
             "avg_launch_us": round(1e6 * l2, 2),
             "traffic_bytes_per_launch": tb,
             "measured_DRAM_GBs": None if tb is None else round(tb / l2 / 1e9, 1)}
+        # the nine 1600x200 configurations (superheat x inlet speed)
+        sweep = []
+        for sh, uin in W.C2_SWEEP:
+            dc = make_domain(L, W, W.c2(superheat=sh, u_in=uin), storage, stream)
+            wc, _ = time_domain(torch, dc, 2000, 200)
+            dc.close()
+            sweep.append({"superheat": sh, "u_in": uin, "MLUPS": round(nodes * 2000 / wc / 1e6, 1)})
+        var["channel_1600x200_sweep"] = sweep
+        # size sweep of the FP32 channel (cache-resident to HBM-resident)
+        sizes = []
+        for snx, sny in ((200, 50), (400, 100), (800, 200), (1600, 400), (3200, 800), (8192, 1024),
+                         (8192, 2048)):
+            cs = W.Channel(nx=snx, ny=sny, heater_len=max(2, int(0.4 * sny)))
+            ds = make_domain(L, W, cs, L.STORE_F32_DEV, stream)
+            ns = 4000 if snx * sny < 1e6 else 200
+            ws, _ = time_domain(torch, ds, ns, ns // 10)
+            ls = launch_duration(torch, ds, 50)
+            ds.close()
+            sizes.append({"nx": snx, "ny": sny, "MLUPS": round(snx * sny * ns / ws / 1e6, 1),
+                          "kernel_alg_GBs": round(144 * snx * sny / ls / 1e9, 1)})
+        var["size_sweep_f32"] = sizes
         # half-precision deviation storage at the headline size
         for name, st in (("F16_DEV", L.STORE_F16_DEV), ("BF16_DEV", L.STORE_BF16_DEV)):
             dh = make_domain(L, W, cfg, st, stream)
@@ -226,6 +247,13 @@ def main():
         var["ensemble_64_f32"] = {"nodes": tot, "steps": nb,
                                   "batched_MLUPS": round(tot * nb / t_batch / 1e6, 1),
                                   "one_at_a_time_MLUPS": round(tot * nb / t_solo / 1e6, 1)}
+        # serving stream: Poisson arrivals through the continuous-batching
+        # server (a shortened form of the 256-request stream; see
+        # paper_2009_05264_amd/serve_stream.py for the full one)
+        from paper_2009_05264_amd import serve_stream as SS
+
+        var["serving_stream_48req"] = SS.run_stream(n=48, rate=8.0, lo=2000, hi=10000, p16=0.5, seed=5,
+                                                    cap_gb=200.0, quantum=500, stream=stream)
         # device copy ceiling (read + write bytes / time)
         n = 1 << 28
         a = torch.empty(n // 4, dtype=torch.float32, device="cuda")

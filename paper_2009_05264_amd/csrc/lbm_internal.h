@@ -41,7 +41,7 @@ struct DevDomain {
   float rho_ref, T_ref, T_iso, rho_mid;
   float pad4[2];
   // buffers
-  void* buf[2];         // state A/B: 9 f planes then 9 g planes (g absent when isothermal)
+  void* buf[2];         // state A/B: 9 planes [ny][pitch] of (f_i, g_i) pairs (f_i alone when isothermal)
   float* fold[2];       // convective-outlet memory [3][ny] (deviation form), A/B
   const float* psiw[2]; // pseudopotential of the false wall density, S and N, [nx]
   const float* Tw[2];   // wall temperature, S and N, [nx]

@@ -15,7 +15,8 @@
 // Three rotating row slots live in registers; x neighbours come from
 // cross-lane shuffles.  No LDS, no barrier.  All arithmetic is FP32 on the
 // deviations f_i - w_i rho_ref, g_i - w_i T_ref; the HBM storage is FP32,
-// FP16 or BF16 (template parameter).
+// FP16 or BF16 (template parameter), one plane per direction holding the
+// (f_i, g_i) pair of every node (f_i alone for isothermal domains).
 //
 // Reductions for the diagnostics and for the mean density of the buoyancy
 // force are fixed-order FP64: each tile writes its partial sums; in the next
@@ -112,6 +113,71 @@ struct BufIO<LBM_STORE_F32> {
 };
 template <>
 struct BufIO<LBM_STORE_F32_DEV> : BufIO<LBM_STORE_F32> {};
+
+// Thermal domains store f_i and g_i of a node side by side (one 8-byte or
+// 4-byte pair), so one load or store moves both distributions of a
+// direction.  IMM is an offset in pairs.
+template <int S>
+struct PairIO;
+template <>
+struct PairIO<LBM_STORE_F32> {
+  static constexpr int E2 = 8;
+  template <int IMM>
+  static __device__ __forceinline__ void ld(Rsrc r, int voff, int soff, float& f, float& g) {
+    const unsigned long long w =
+        __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, voff + IMM * E2, soff, 0));
+    f = __uint_as_float((uint32_t)w);
+    g = __uint_as_float((uint32_t)(w >> 32));
+  }
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
+    // Empty register constraint: keeps the pair operands as register values,
+    // so that the packing below is not rewritten into a widened memory load
+    // of the source arrays (which would pin them in private memory).
+    asm("" : "+v"(f), "+v"(g));
+    const unsigned long long w = (unsigned long long)__float_as_uint(f) |
+                                 ((unsigned long long)__float_as_uint(g) << 32);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, w), r, voff, soff, 0);
+  }
+};
+template <>
+struct PairIO<LBM_STORE_F32_DEV> : PairIO<LBM_STORE_F32> {};
+template <>
+struct PairIO<LBM_STORE_F16_DEV> {
+  static constexpr int E2 = 4;
+  template <int IMM>
+  static __device__ __forceinline__ void ld(Rsrc r, int voff, int soff, float& f, float& g) {
+    const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * E2, soff, 0);
+    f = (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xFFFFu));
+    g = (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
+  }
+  static __device__ __forceinline__ uint32_t enc(float v) {
+    v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
+    return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v);
+  }
+  static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
+    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, 0);
+  }
+};
+template <>
+struct PairIO<LBM_STORE_BF16_DEV> {
+  static constexpr int E2 = 4;
+  template <int IMM>
+  static __device__ __forceinline__ void ld(Rsrc r, int voff, int soff, float& f, float& g) {
+    const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * E2, soff, 0);
+    f = __uint_as_float(u << 16);
+    g = __uint_as_float(u & 0xFFFF0000u);
+  }
+  static __device__ __forceinline__ uint32_t enc(float v) {
+    v = fminf(fmaxf(v, -3.3895313892515355e38f), 3.3895313892515355e38f);
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return u >> 16;
+  }
+  static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
+    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, 0);
+  }
+};
 template <>
 struct BufIO<LBM_STORE_F16_DEV> {
   template <int IMM>
@@ -153,57 +219,57 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v,
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // Peng-Robinson EOS (Eq. 12), pseudopotential (Eq. 11), (dp/dT)_rho.
+// One reciprocal square root gives both sqrt(T/Tc) = T / sqrt(T Tc) and the
+// 1 / sqrt(T Tc) of d alpha / dT; one reciprocal of the product of the two
+// denominators gives both of their reciprocals.
 __device__ __forceinline__ void eos(DRef D, float rho, float T, float& p, float& psi,
                                     float& dpdT, int& clamped) {
-  const float s = fsqrt(T * D.inv_Tc);
+  const float rs = __builtin_amdgcn_rsqf(T * D.Tc);  // 1 / sqrt(T Tc)
+  const float s = T * rs;                             // sqrt(T / Tc)
   const float sa = 1.f + D.kappa * (1.f - s);
   const float alpha = sa * sa;
   const float br = D.b * rho;
-  const float r1 = rcp(1.f - br);
-  const float r2 = rcp(1.f + br * (2.f - br));
+  const float d1 = 1.f - br;
+  const float d2 = 1.f + br * (2.f - br);
+  const float rp = rcp(d1 * d2);
+  const float r1 = d2 * rp;  // 1 / (1 - b rho)
+  const float r2 = d1 * rp;  // 1 / (1 + 2 b rho - b^2 rho^2)
   const float ar2 = D.a * rho * rho * r2;
   p = rho * D.R * T * r1 - alpha * ar2;
   float q = (p - rho * (1.f / 3.f)) * D.c0g2;
   clamped = !(q >= 0.f);
   q = clamped ? 0.f : q;
   psi = fsqrt(q);
-  dpdT = rho * D.R * r1 + ar2 * D.kappa * sa * rcp(s * D.Tc);
+  dpdT = rho * D.R * r1 + ar2 * D.kappa * sa * rs;
 }
 
 // Raw-buffer pull.  The resource base sits one row and one column before
-// the buffer, so the source of direction i is: plane offset (SGPR) + the
-// row-and-column offset of its source row at the lane's column (VGPR) +
-// (1 - cx_i) elements (immediate).  vf[i] / vg[i] are the per-lane offsets of
-// the f / g source of direction i, so[i] the plane offsets (0-8 f, 9-17 g).
-template <int S, int I>
-__device__ __forceinline__ float ld_dir(Rsrc rs, int voff, int soff) {
+// the buffer (and, for column-edge tiles, a further offset below it, see
+// TileRun), so the source of direction i is: plane offset so[i] (SGPR) +
+// the row-and-column offset vf[i] of its source row at the lane's column
+// (VGPR) + (1 - cx_i) elements (immediate).  Thermal domains load the
+// (f_i, g_i) pair of the source in one access; isothermal ones f_i alone.
+template <int S, bool TH, int I>
+__device__ __forceinline__ void ld_dir(Rsrc rs, int voff, int soff, float& f, float& g) {
   constexpr int imm = 1 - CX[I];
-  return BufIO<S>::template ld<imm>(rs, voff, soff);
+  if (TH)
+    PairIO<S>::template ld<imm>(rs, voff, soff, f, g);
+  else
+    f = BufIO<S>::template ld<imm>(rs, voff, soff);
 }
 
 template <int S, bool TH>
-__device__ __forceinline__ void pull_dirs(Rsrc rs, const int (&vf)[9], const int (&vg)[9],
-                                          const int (&so)[18], float (&h)[9], float (&k)[9]) {
-  h[0] = ld_dir<S, 0>(rs, vf[0], so[0]);
-  h[1] = ld_dir<S, 1>(rs, vf[1], so[1]);
-  h[2] = ld_dir<S, 2>(rs, vf[2], so[2]);
-  h[3] = ld_dir<S, 3>(rs, vf[3], so[3]);
-  h[4] = ld_dir<S, 4>(rs, vf[4], so[4]);
-  h[5] = ld_dir<S, 5>(rs, vf[5], so[5]);
-  h[6] = ld_dir<S, 6>(rs, vf[6], so[6]);
-  h[7] = ld_dir<S, 7>(rs, vf[7], so[7]);
-  h[8] = ld_dir<S, 8>(rs, vf[8], so[8]);
-  if (TH) {
-    k[0] = ld_dir<S, 0>(rs, vg[0], so[9]);
-    k[1] = ld_dir<S, 1>(rs, vg[1], so[10]);
-    k[2] = ld_dir<S, 2>(rs, vg[2], so[11]);
-    k[3] = ld_dir<S, 3>(rs, vg[3], so[12]);
-    k[4] = ld_dir<S, 4>(rs, vg[4], so[13]);
-    k[5] = ld_dir<S, 5>(rs, vg[5], so[14]);
-    k[6] = ld_dir<S, 6>(rs, vg[6], so[15]);
-    k[7] = ld_dir<S, 7>(rs, vg[7], so[16]);
-    k[8] = ld_dir<S, 8>(rs, vg[8], so[17]);
-  }
+__device__ __forceinline__ void pull_dirs(Rsrc rs, const int (&vf)[9], const int (&so)[9], float (&h)[9],
+                                          float (&k)[9]) {
+  ld_dir<S, TH, 0>(rs, vf[0], so[0], h[0], k[0]);
+  ld_dir<S, TH, 1>(rs, vf[1], so[1], h[1], k[1]);
+  ld_dir<S, TH, 2>(rs, vf[2], so[2], h[2], k[2]);
+  ld_dir<S, TH, 3>(rs, vf[3], so[3], h[3], k[3]);
+  ld_dir<S, TH, 4>(rs, vf[4], so[4], h[4], k[4]);
+  ld_dir<S, TH, 5>(rs, vf[5], so[5], h[5], k[5]);
+  ld_dir<S, TH, 6>(rs, vf[6], so[6], h[6], k[6]);
+  ld_dir<S, TH, 7>(rs, vf[7], so[7], h[7], k[7]);
+  ld_dir<S, TH, 8>(rs, vf[8], so[8], h[8], k[8]);
 }
 
 // MRT collision with exact-difference forcing, in deviation form.  b_k =
@@ -262,11 +328,23 @@ __device__ __forceinline__ void collide_g(DRef D, const float k[9], float dT, fl
   const float u2 = uax * uax + uay * uay;
   const float base = om * dT + phi - 1.5f * tT * u2;
   const float keep = 1.f - om;
+  // c_i . u_act, written out (no multiplications by zero components)
+  const float cu[9] = {0.f, uax, uay, -uax, -uay, uax + uay, uay - uax, -uax - uay, uax - uay};
+  ks[0] = keep * k[0] + WF[0] * base;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const float cu = (float)CX[i] * uax + (float)CY[i] * uay;
-    ks[i] = keep * k[i] + WF[i] * (base + tT * cu * (3.f + 4.5f * cu));
-  }
+  for (int i = 1; i < 9; ++i) ks[i] = keep * k[i] + WF[i] * (base + tT * cu[i] * (3.f + 4.5f * cu[i]));
+}
+
+// Neighbour exchange across the wavefront by DPP row moves: shfl_dn1 gives
+// lane i the value of lane i + 1, shfl_up1 that of lane i - 1; the end
+// lane without a source keeps its own value (as __shfl_down / __shfl_up).
+__device__ __forceinline__ float shfl_dn1(float v) {
+  const int i = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(i, i, 0x130, 0xF, 0xF, false));  // wave_shl:1
+}
+__device__ __forceinline__ float shfl_up1(float v) {
+  const int i = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(i, i, 0x138, 0xF, 0xF, false));  // wave_shr:1
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -312,11 +390,14 @@ __device__ __forceinline__ void sum_partials(const double* parts, int stride, in
 // outlet sources).  The value-level parts of the rules (anti-bounce-back
 // temperatures, Zou-He, convective blend) are applied when the row is
 // consumed.
-template <int S, int MODE, int KIND, bool TH>
+template <int S, int MODE, int KIND, bool TH, int NB>
 struct TileRun {
   static constexpr bool EDGE = KIND != 0;  // rows near a wall or the periodic seam
   static constexpr bool XE = KIND == 2;    // the tile reaches column 0 or nx - 1
+  static_assert(NB == 2 || NB == 3, "prefetch depth");
   using C = Codec<S>;
+  // bytes per plane element: an (f, g) pair, or f alone when isothermal
+  static constexpr int E2 = TH ? PairIO<S>::E2 : C::E;
   DRef D;
   const Tile AS4& tl;
   int lane, phase, nx, ny, x, xc;
@@ -324,7 +405,8 @@ struct TileRun {
   const float* fold;
   float* fold_dst;
   Rsrc rs, rd;
-  int pitch, sst[18];
+  int pitch, sst[9];  // plane byte offsets
+  int kb;             // extra base offset of the pull resource (column-edge tiles)
   float gbar;
   int r_end;
   // boundary tiles: -1 in lanes whose column is 0 (mL) / nx-1 (mR)
@@ -338,9 +420,10 @@ struct TileRun {
   // reductions
   double acc_mass = 0.0, acc_energy = 0.0, acc_q = 0.0, acc_pin = 0.0, acc_pout = 0.0;
   int acc_vap = 0, acc_clamp = 0, acc_nf = 0;
-  // prefetched rows, double-buffered: a loaded register is first touched one
-  // iteration after its load was issued; pfo: outlet memory of that row
-  float ph[2][9], pk[2][9], pfo[2][3];
+  // prefetched rows in NB rotating buffers: the loads of row r + NB - 1 are
+  // issued while row r is consumed, so a loaded register is first touched
+  // NB - 1 iterations after its load was issued; pfo: outlet memory of the row
+  float ph[NB][9], pk[NB][9], pfo[NB][3];
   // row a (r)
   float a_drho = 0.f, a_jx = 0.f, a_jy = 0.f, a_dT = 0.f, a_psi = 0.f, a_A = 0.f, a_B = 0.f, a_dpdT = 0.f;
   bool sa = false;
@@ -348,8 +431,8 @@ struct TileRun {
   float bh[9], bk[9];
   float b_drho = 0.f, b_jx = 0.f, b_jy = 0.f, b_dT = 0.f, b_psi = 0.f, b_A = 0.f, b_B = 0.f, b_dpdT = 0.f;
   bool sb = false;
-  // row c (r-2)
-  float ck[9];
+  // row c (r-2); fc: post-collision f of row c, stored with its g
+  float ck[9], fc[9];
   float c_A = 0.f, c_B = 0.f, c_dT = 0.f, c_dpdT = 0.f, c_irho = 0.f, c_uax = 0.f, c_uay = 0.f;
   bool sc = false;
   // row d (r-3)
@@ -375,12 +458,15 @@ struct TileRun {
     mL = XE && xc == 0 ? -1 : 0;
     mR = XE && xc == nx - 1 ? -1 : 0;
     pitch = D.pitch;
-    constexpr int E = C::E;
     const int plane = (int)D.plane;
-    rs = make_rsrc((const char*)D.buf[phase] - (pitch + 1) * E);
-    rd = make_rsrc(D.buf[phase ^ 1]);
 #pragma unroll
-    for (int i = 0; i < 18; ++i) sst[i] = i * plane * E;
+    for (int i = 0; i < 9; ++i) sst[i] = i * plane * E2;
+    // Column-edge tiles of thermal domains redirect some inlet sources to a
+    // lower plane (a negative per-lane offset): their resource base sits two
+    // planes lower still, so every per-lane offset stays non-negative.
+    kb = XE && TH ? 2 * sst[1] : 0;
+    rs = make_rsrc((const char*)D.buf[phase] - kb - (pitch + 1) * E2);
+    rd = make_rsrc(D.buf[phase ^ 1]);
     // mean density two states back: sum of the level-1 slices written by the
     // previous launch's finalizers
     double mass = lane < kFin ? D.l1[phase][lane * kPartials + P_MASS] : 0.0;
@@ -388,9 +474,14 @@ struct TileRun {
     gbar = (float)((double)D.rho_ref - mass / ((double)nx * (double)ny));
     r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) ph[0][i] = pk[0][i] = ph[1][i] = pk[1][i] = bh[i] = bk[i] = ck[i] = 0.f;
+    for (int i = 0; i < 9; ++i) bh[i] = bk[i] = ck[i] = fc[i] = 0.f;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) pfo[0][i] = pfo[1][i] = 0.f;
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) ph[b][i] = pk[b][i] = 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) pfo[b][i] = 0.f;
+    }
     if (EDGE) {
       // Every load and store of a boundary tile is issued unconditionally
       // (offset kDrop where it has nothing to move), so that the march keeps
@@ -424,71 +515,64 @@ struct TileRun {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
   }
 
+  // Pull row rr into buffer B.  A row past the tile's last one (the
+  // look-ahead of the final iterations) is issued with offset kDrop, which
+  // moves nothing, so every iteration has the same memory operations.
   template <int B>
   __device__ __forceinline__ void fetch(int rr) {
-    constexpr int E = C::E;
-    int vf[9], vg[9], so[18];
+    const bool past = rr > r_end;
+    int vf[9], so[9];
 #pragma unroll
-    for (int i = 0; i < 18; ++i) so[i] = sst[i];
+    for (int i = 0; i < 9; ++i) so[i] = sst[i];
     if (!EDGE) {
-      const int v0 = (rr * pitch + xc) * E;
-      const int vr[3] = {v0, v0 + pitch * E, v0 + 2 * pitch * E};
+      const int v0 = (rr * pitch + xc) * E2;
+      const int vr[3] = {past ? kDrop : v0, past ? kDrop : v0 + pitch * E2, past ? kDrop : v0 + 2 * pitch * E2};
 #pragma unroll
-      for (int i = 0; i < 9; ++i) vf[i] = vg[i] = vr[1 - CY[i]];
+      for (int i = 0; i < 9; ++i) vf[i] = vr[1 - CY[i]];
     } else {
       // a solid row (beyond a wall) moves nothing: every offset is kDrop
-      const bool solid = walls && (rr < 0 || rr >= ny);
+      const bool solid = past || (walls && (rr < 0 || rr >= ny));
       const int ro = walls ? clampi(rr, 0, ny - 1) : wrap1(rr, ny);
       const bool wS = walls && ro == 0, wN = walls && ro == ny - 1;
       const int rsr = wS ? ro : (ro == 0 ? ny - 1 : ro - 1);
       const int rnr = wN ? ro : (ro == ny - 1 ? 0 : ro + 1);
-      const int PE = pitch * E;
+      const int PE = pitch * E2;
       const int R0 = (rsr + 1) * PE, R1 = (ro + 1) * PE, R2 = (rnr + 1) * PE;
-      const int xe = xc * E;
+      const int xe = xc * E2 + kb;
       const int vr[3] = {solid ? kDrop : xe + R0, solid ? kDrop : xe + R1, solid ? kDrop : xe + R2};
 #pragma unroll
-      for (int i = 0; i < 9; ++i) vf[i] = vg[i] = vr[1 - CY[i]];
+      for (int i = 0; i < 9; ++i) vf[i] = vr[1 - CY[i]];
       // bounce-back sources: the opposite direction at the node itself
       if (wS) {
         so[2] = sst[4];
-        so[5] = sst[7] + E;
-        so[6] = sst[8] - E;
-        so[11] = sst[13];
-        so[14] = sst[16] + E;
-        so[15] = sst[17] - E;
+        so[5] = sst[7] + E2;
+        so[6] = sst[8] - E2;
       }
       if (wN) {
         so[4] = sst[2];
-        so[7] = sst[5] - E;
-        so[8] = sst[6] + E;
-        so[13] = sst[11];
-        so[16] = sst[14] - E;
-        so[17] = sst[15] + E;
+        so[7] = sst[5] - E2;
+        so[8] = sst[6] + E2;
       }
       if (XE) {
         const int mLr = solid ? 0 : mL, mRr = solid ? 0 : mR;
         const int P = sst[1];
-        int cL1, cL5, cL8, gL1, gL5, gL8, cR3, cR6, cR7;
+        int cL1, cL5, cL8, cR3, cR6, cR7;
         if (chan) {
-          // inlet column: the f slots of 1, 5, 8 (replaced by Zou-He) carry g
-          // of 3, 7, 6 at the node itself for the anti-bounce-back rule; the g
-          // slots keep their in-buffer ghost source.  Outlet column: the
-          // sources of 3, 6, 7 move from column nx to column nx-1.
-          cL1 = TH ? 11 * P + E : 0;
-          cL5 = (TH && !wS) ? 11 * P + E + (R1 - R0) : 0;
-          cL8 = (TH && !wN) ? 7 * P + E + (R1 - R2) : 0;
-          gL1 = gL5 = gL8 = 0;
-          cR3 = -E;
-          cR6 = wS ? 0 : -E;
-          cR7 = wN ? 0 : -E;
+          // Inlet column: the sources of 1, 5, 8 (ghosts; f is set by Zou-He)
+          // move to the pairs of 3, 7, 6 at the node itself, whose g the
+          // anti-bounce-back rule needs.  Outlet column: the sources of 3,
+          // 6, 7 move from column nx to column nx-1.
+          cL1 = TH ? 2 * P + E2 : 0;
+          cL5 = (TH && !wS) ? 2 * P + E2 + (R1 - R0) : 0;
+          cL8 = (TH && !wN) ? -2 * P + E2 + (R1 - R2) : 0;
+          cR3 = -E2;
+          cR6 = wS ? 0 : -E2;
+          cR7 = wN ? 0 : -E2;
         } else {
-          const int W = nx * E;
+          const int W = nx * E2;
           cL1 = W;
           cL5 = wS ? 0 : W;
           cL8 = wN ? 0 : W;
-          gL1 = cL1;
-          gL5 = cL5;
-          gL8 = cL8;
           cR3 = -W;
           cR6 = wS ? 0 : -W;
           cR7 = wN ? 0 : -W;
@@ -496,22 +580,16 @@ struct TileRun {
         vf[1] += mLr & cL1;
         vf[5] += mLr & cL5;
         vf[8] += mLr & cL8;
-        vg[1] += mLr & gL1;
-        vg[5] += mLr & gL5;
-        vg[8] += mLr & gL8;
         vf[3] += mRr & cR3;
         vf[6] += mRr & cR6;
         vf[7] += mRr & cR7;
-        vg[3] += mRr & cR3;
-        vg[6] += mRr & cR6;
-        vg[7] += mRr & cR7;
         const int vo = has_out && !solid ? ro * 4 : kDrop;
         pfo[B][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 0, 0));
         pfo[B][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, ny * 4, 0));
         pfo[B][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rfo, vo, 2 * ny * 4, 0));
       }
     }
-    pull_dirs<S, TH>(rs, vf, vg, so, ph[B], pk[B]);
+    pull_dirs<S, TH>(rs, vf, so, ph[B], pk[B]);
   }
 
   // Value-level boundary rules of row r (own row ro) on the pulled values.
@@ -534,9 +612,10 @@ struct TileRun {
       const float u = D.u_in;
       if (TH) {
         const float gin = D.in_geq - D.T_ref;
-        k[1] = -h[1] + 2.f * WF[1] * gin;
-        if (!wS) k[5] = -h[5] + 2.f * WF[5] * gin;
-        if (!wN) k[8] = -h[8] + 2.f * WF[8] * gin;
+        // the pairs pulled for 1, 5, 8 are those of 3, 7, 6 at this node
+        k[1] = -k[1] + 2.f * WF[1] * gin;
+        if (!wS) k[5] = -k[5] + 2.f * WF[5] * gin;
+        if (!wN) k[8] = -k[8] + 2.f * WF[8] * gin;
       }
       const float rin = (D.rho_ref + h[0] + h[2] + h[4] + 2.f * (h[3] + h[6] + h[7])) * D.inv_1mu;
       const float d24 = 0.5f * (h[2] - h[4]);
@@ -558,12 +637,11 @@ struct TileRun {
   // B: prefetch buffer holding row r (row r + 1 goes to the other one).
   template <bool ST2, bool OUT2, bool ST3, bool PF, int B>
   __device__ __forceinline__ void iter(int r) {
-    constexpr int E = C::E;
     float* ah = ph[B];
     float* ak = pk[B];
     // ---------------- stage 1: row r
     sa = walls && (r < 0 || r >= ny);
-    if (PF) fetch<B ^ 1>(min(r + 1, r_end));
+    if (PF) fetch<(B + NB - 1) % NB>(r + NB - 1);
     int fo_off = kDrop;  // outlet memory store of this row
     if (sa) {
       const float psiW = r < 0 ? psiS : psiN;
@@ -573,12 +651,13 @@ struct TileRun {
     } else {
       const int ry = (!EDGE || walls) ? r : wrap1(r, ny);
       if (EDGE) fix_row(ry, ah, ak, pfo[B]);
-      float drho = 0.f, dT = 0.f;
+      float drho = ah[0], dT;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) drho += ah[i];
+      for (int i = 1; i < 9; ++i) drho += ah[i];
       if (TH) {
+        dT = ak[0];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) dT += ak[i];
+        for (int i = 1; i < 9; ++i) dT += ak[i];
       } else {
         dT = D.T_iso - D.T_ref;
       }
@@ -621,6 +700,9 @@ struct TileRun {
 
     // ---------------- stage 2: row q = r - 1 (b): force, u_act, f collision
     float b_uax = 0.f, b_uay = 0.f, b_irho = 0.f;
+    float fnew[9];  // post-collision f of row q
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fnew[i] = 0.f;
     if (ST2 && !sb) {
       float Fx = 0.f, Fy = 0.f;
       if (!D.single_phase) {
@@ -628,10 +710,10 @@ struct TileRun {
         const float VB = D.G1 * b_B + D.G2 * (a_B + c_B);
         const float DA = a_A - c_A;
         const float DB = a_B - c_B;
-        const float VAr = __shfl_down(VA, 1, kWave), VAl = __shfl_up(VA, 1, kWave);
-        const float VBr = __shfl_down(VB, 1, kWave), VBl = __shfl_up(VB, 1, kWave);
-        const float DAr = __shfl_down(DA, 1, kWave), DAl = __shfl_up(DA, 1, kWave);
-        const float DBr = __shfl_down(DB, 1, kWave), DBl = __shfl_up(DB, 1, kWave);
+        const float VAr = shfl_dn1(VA), VAl = shfl_up1(VA);
+        const float VBr = shfl_dn1(VB), VBl = shfl_up1(VB);
+        const float DAr = shfl_dn1(DA), DAl = shfl_up1(DA);
+        const float DBr = shfl_dn1(DB), DBl = shfl_up1(DB);
         const float SAx = VAr - VAl, SBx = VBr - VBl;
         const float SAy = D.G1 * DA + D.G2 * (DAr + DAl);
         const float SBy = D.G1 * DB + D.G2 * (DBr + DBl);
@@ -657,20 +739,29 @@ struct TileRun {
             D.out[3][o] = D.T_ref + b_dT;
           }
         } else {
-          float hs[9];
-          collide_f(D, bh, b_drho, b_jx, b_jy, ux, uy, Fx, Fy, b_irho, hs);
-          const int voff = interior ? (q * pitch + x) * E : kDrop;
-#pragma unroll
-          for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[i], hs[i]);
+          collide_f(D, bh, b_drho, b_jx, b_jy, ux, uy, Fx, Fy, b_irho, fnew);
         }
       }
     }
+    // Isothermal: f alone is stored here.  Every step iteration issues the
+    // same nine stores (offset kDrop when there is nothing to store), so the
+    // count of memory operations between a row's loads and their use is the
+    // same on every path into the loop and the waits stay partial.
+    if (MODE == MODE_STEP && !TH) {
+      const int voff = OUT2 && !sb && interior ? ((r - 1) * pitch + x) * E2 : kDrop;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[i], fnew[i]);
+    }
 
     // ---------------- stage 3: row c = r - 2: source and g collision
+    if (MODE == MODE_STEP && TH && !ST3) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) PairIO<S>::st(rd, kDrop, sst[i], 0.f, 0.f);  // same count, see above
+    }
     if (MODE == MODE_STEP && TH && ST3) {
       const int cr = r - 2;
-      float uxl = __shfl_up(c_uax, 1, kWave);
-      float uxr = __shfl_down(c_uax, 1, kWave);
+      float uxl = shfl_up1(c_uax);
+      float uxr = shfl_dn1(c_uax);
       if (xlo) uxl = c_uax;
       if (xhi) uxr = c_uax;
       const float dux = 0.5f * (uxr - uxl);
@@ -682,9 +773,9 @@ struct TileRun {
       const float phi = T * (div_adv - c_dpdT * c_irho * D.inv_cv * div_mass);
       float ks[9];
       collide_g(D, ck, c_dT, T, c_uax, c_uay, phi, ks);
-      const int voff = interior ? (cr * pitch + x) * E : kDrop;
+      const int voff = interior ? (cr * pitch + x) * E2 : kDrop;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[9 + i], ks[i]);
+      for (int i = 0; i < 9; ++i) PairIO<S>::st(rd, voff, sst[i], fc[i], ks[i]);
     }
 
     // ---------------- rotate: d <- c <- b <- a
@@ -695,6 +786,7 @@ struct TileRun {
       ck[i] = bk[i];
       bk[i] = ak[i];
       bh[i] = ah[i];
+      if (MODE == MODE_STEP && TH) fc[i] = fnew[i];
     }
     c_A = b_A;
     c_B = b_B;
@@ -715,40 +807,44 @@ struct TileRun {
     sb = sa;
   }
 
-  __device__ __forceinline__ void run() {
-    const int y0 = tl.y0, y1 = tl.y1;
-    fetch<0>(y0 - 2);
-    iter<false, false, false, true, 0>(y0 - 2);
-    iter<false, false, false, true, 1>(y0 - 1);
-    if (MODE == MODE_STEP) {
-      iter<true, false, false, true, 0>(y0);
-      iter<true, true, false, true, 1>(y0 + 1);
-      // steady state: rows y0+2 .. y1, two per trip (buffers 0, 1)
-      int r = y0 + 2;
-      for (; r + 1 <= y1; r += 2) {
-        iter<true, true, true, true, 0>(r);
-        iter<true, true, true, true, 1>(r + 1);
-      }
-      if (r <= y1) {
-        iter<true, true, true, true, 0>(r);
-        iter<true, false, true, false, 1>(y1 + 1);
-      } else {
-        iter<true, false, true, false, 0>(y1 + 1);
-      }
-    } else {
-      iter<true, false, false, true, 0>(y0);
-      int r = y0 + 1;
-      for (; r + 1 < y1; r += 2) {
-        iter<true, true, false, true, 1>(r);
-        iter<true, true, false, true, 0>(r + 1);
-      }
-      if (r < y1) {
-        iter<true, true, false, true, 1>(r);
-        iter<true, true, false, false, 0>(y1);
-      } else {
-        iter<true, true, false, false, 1>(y1);
-      }
+  // Iterations from row r (buffer B0 holds row r) to r_end, NB per trip.
+  // When stepping, the final iteration (r_end = y1 + 1) only finishes stage
+  // 3 of row y1 - 1: its stage-2 row y1 belongs to the next tile.
+  template <int B0>
+  __device__ __forceinline__ void steady(int r) {
+    constexpr bool ST3 = MODE == MODE_STEP;
+    const int r_out = MODE == MODE_STEP ? r_end - 1 : r_end;  // last row-r with stage-2 output
+    for (; r + NB - 1 <= r_out; r += NB) {
+      iter<true, true, ST3, true, B0 % NB>(r);
+      iter<true, true, ST3, true, (B0 + 1) % NB>(r + 1);
+      if (NB == 3) iter<true, true, ST3, true, (B0 + 2) % NB>(r + 2);
     }
+    const int rem = r_out - r + 1;  // 0 .. NB-1
+    if (rem == 0) {
+      if (MODE == MODE_STEP) iter<true, false, ST3, true, B0 % NB>(r);
+    } else if (rem == 1) {
+      iter<true, true, ST3, true, B0 % NB>(r);
+      if (MODE == MODE_STEP) iter<true, false, ST3, true, (B0 + 1) % NB>(r + 1);
+    } else if (NB == 3) {
+      iter<true, true, ST3, true, B0 % NB>(r);
+      iter<true, true, ST3, true, (B0 + 1) % NB>(r + 1);
+      if (MODE == MODE_STEP) iter<true, false, ST3, true, (B0 + 2) % NB>(r + 2);
+    }
+  }
+
+  __device__ __forceinline__ void run() {
+    // Rows y0-2 .. r_end are pulled (r_end = y1 + 1 when stepping: stage 3
+    // of the last row needs u_act of the row above it).  Stage 2 starts at
+    // the third row, its collision output at the fourth, stage 3 at the
+    // fifth.
+    const int y0 = tl.y0;
+    fetch<0>(y0 - 2);
+    if (NB == 3) fetch<1 % NB>(y0 - 1);
+    iter<false, false, false, true, 0>(y0 - 2);
+    iter<false, false, false, true, 1 % NB>(y0 - 1);
+    iter<true, false, false, true, 2 % NB>(y0);
+    iter<true, true, false, true, 3 % NB>(y0 + 1);
+    steady<4 % NB>(y0 + 2);
     // tile partial sums (fixed order: lane tree)
     double v[kPartials] = {acc_mass, acc_energy, acc_q, (double)acc_vap, (double)acc_clamp,
                            (double)acc_nf, acc_pin, acc_pout};
@@ -806,6 +902,9 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return k * q + min(k, rem) + i;
 }
 
+// Row buffers of interior tiles (look-ahead kDepthInterior - 1 rows).
+constexpr int kDepthInterior = 3;
+
 template <int S, int MODE>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel(
     const Tile* __restrict__ tiles, int ntiles, const FinEntry* __restrict__ fins, int nfin,
@@ -827,13 +926,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     const bool xin = tl.x0 >= 3 && tl.x0 + kWave - 2 < D.nx;
     const bool yin = tl.y0 - 2 >= 1 && r_end <= D.ny - 2;
     if (D.isothermal) {
-      if (!xin) TileRun<S, MODE, 2, false>(tl, gphase).run();
-      else if (!yin) TileRun<S, MODE, 1, false>(tl, gphase).run();
-      else TileRun<S, MODE, 0, false>(tl, gphase).run();
+      if (!xin) TileRun<S, MODE, 2, false, 2>(tl, gphase).run();
+      else if (!yin) TileRun<S, MODE, 1, false, 2>(tl, gphase).run();
+      else TileRun<S, MODE, 0, false, kDepthInterior>(tl, gphase).run();
     } else {
-      if (!xin) TileRun<S, MODE, 2, true>(tl, gphase).run();
-      else if (!yin) TileRun<S, MODE, 1, true>(tl, gphase).run();
-      else TileRun<S, MODE, 0, true>(tl, gphase).run();
+      if (!xin) TileRun<S, MODE, 2, true, 2>(tl, gphase).run();
+      else if (!yin) TileRun<S, MODE, 1, true, 2>(tl, gphase).run();
+      else TileRun<S, MODE, 0, true, kDepthInterior>(tl, gphase).run();
     }
   }
 }
@@ -875,12 +974,13 @@ __global__ void init_kernel(DevDomain D, const double* rho0, const double* T0, d
     const uint32_t idx = (uint32_t)(y * D.pitch + x);
     const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    for (int i = 0; i < 9; ++i)
-      C::st(buf, (uint32_t)(i * (uint32_t)D.plane + idx) * C::E, (float)(W[i] * (r - (double)D.rho_ref)));
-    if (!D.isothermal)
-      for (int i = 0; i < 9; ++i)
-        C::st(buf, (uint32_t)((9 + i) * (uint32_t)D.plane + idx) * C::E,
-              (float)(W[i] * (t - (double)D.T_ref)));
+    // plane i holds f_i (isothermal) or the (f_i, g_i) pair of each node
+    const uint32_t E2 = D.isothermal ? C::E : 2 * C::E;
+    for (int i = 0; i < 9; ++i) {
+      const uint32_t o = (uint32_t)(i * (uint32_t)D.plane + idx) * E2;
+      C::st(buf, o, (float)(W[i] * (r - (double)D.rho_ref)));
+      if (!D.isothermal) C::st(buf, o + C::E, (float)(W[i] * (t - (double)D.T_ref)));
+    }
     if (D.bc_x == LBM_BCX_CHANNEL && x == D.nx - 1) {
       D.fold[b][0 * D.ny + y] = (float)(W[3] * (r - (double)D.rho_ref));
       D.fold[b][1 * D.ny + y] = (float)(W[6] * (r - (double)D.rho_ref));
@@ -889,10 +989,21 @@ __global__ void init_kernel(DevDomain D, const double* rho0, const double* T0, d
   }
 }
 
-__global__ void copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src, long long n4) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4;
-       i += (long long)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+// Streaming copy: four 16-byte loads in flight per thread before their
+// stores, non-temporal stores.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_kernel(vf4* __restrict__ dst, const vf4* __restrict__ src,
+                                                   long long n4) {
+  const long long st = (long long)gridDim.x * blockDim.x;
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i + 3 * st < n4; i += 4 * st) {
+    const vf4 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+    __builtin_nontemporal_store(a, &dst[i]);
+    __builtin_nontemporal_store(b, &dst[i + st]);
+    __builtin_nontemporal_store(c, &dst[i + 2 * st]);
+    __builtin_nontemporal_store(d, &dst[i + 3 * st]);
+  }
+  for (; i < n4; i += st) dst[i] = src[i];
 }
 
 }  // namespace
@@ -947,8 +1058,8 @@ hipError_t lbm_launch_init(int storage, DevDomain*, const DevDomain& dh, const d
 hipError_t lbm_launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const long long n4 = (long long)(bytes / 16);
   const int block = 256;
-  const int grid = (int)std::min<long long>((n4 + block - 1) / block, 256 * 64);
+  const int grid = (int)std::min<long long>((n4 + block - 1) / block, 256 * 8);
   if (n4 > 0)
-    hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(block), 0, s, (float4*)dst, (const float4*)src, n4);
+    hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(block), 0, s, (vf4*)dst, (const vf4*)src, n4);
   return hipGetLastError();
 }

@@ -99,6 +99,16 @@ int validate(const lbm_params* p) {
     return lbm_fail(LBM_E_INVALID, "EOS constants out of range");
   if (p->bc_x == LBM_BCX_CHANNEL && p->nx < 3)
     return lbm_fail(LBM_E_INVALID, "a channel needs nx >= 3");
+  {
+    // The kernels address a state buffer with 32-bit byte offsets: 9 planes
+    // plus the two-plane base shift of the boundary pull must stay below 2 GB.
+    const bool half = p->storage == LBM_STORE_F16_DEV || p->storage == LBM_STORE_BF16_DEV;
+    const double e2 = (half ? 2.0 : 4.0) * (p->isothermal ? 1.0 : 2.0);
+    const double pitch = (double)((p->nx + 31) / 32 * 32);
+    if (11.0 * pitch * (p->ny + 2.0) * e2 > 2147483648.0 - 16777216.0)
+      return lbm_fail(LBM_E_INVALID, "domain %d x %d too large for one state buffer (32-bit offsets)", p->nx,
+                      p->ny);
+  }
   return LBM_OK;
 }
 
@@ -115,8 +125,9 @@ struct Layout {
 int pitch_of(int nx) { return (nx + 31) / 32 * 32; }
 int elem_bytes(int storage) { return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV ? 2 : 4; }
 int max_tiles(const lbm_params& p) {
+  // column-edge strips (at most two) may be cut into single rows
   const int strips = (p.nx + kStripInterior - 1) / kStripInterior;
-  const int t = strips * ((p.ny + kMinTileRows - 1) / kMinTileRows + 2);
+  const int t = std::min(strips, 2) * p.ny + strips * ((p.ny + kMinTileRows - 1) / kMinTileRows + 2);
   return (t + 63) / 64 * 64;  // also the stride of the SoA partial sums
 }
 
@@ -246,23 +257,22 @@ void fill_desc(lbm_domain* d) {
 
 // Rows per tile (automatic).  A tile's march spends four extra row steps
 // filling its pipeline, so short tiles trade redundant pulls for
-// parallelism: domains of up to about 4k four-row tiles use 4 rows (every
-// SIMD of the 256 CUs gets work), larger ones 8 rows (pull overhead 1.5x,
-// still several waves per SIMD).
+// parallelism: 8 rows (pull overhead 1.5x) unless that leaves fewer than
+// about 512 tiles, then 4.
 int lbm_auto_rows(int nx, int ny) {
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
-  return (long long)strips * ((ny + 3) / 4) <= 4096 ? 4 : 8;
+  return (long long)strips * ((ny + 7) / 8) >= 512 ? 8 : 4;
 }
 
 // Row segments [y0, y1) of one strip.  Tiles that run the boundary path do
 // more work per row, so they get fewer rows: strips that reach column 0 or
-// nx - 1 are cut in chunks of rows / 2; the other strips get a 3-row head
+// nx - 1 are cut in chunks of rows / 4 (at least one row); the other strips get a 3-row head
 // and tail (the rows within two of a wall or of the periodic seam) and
 // near-equal chunks of about `rows` in between.
 static void strip_segments(int ny, int rows, bool column_edge, std::vector<std::pair<int, int>>& seg) {
   seg.clear();
   if (column_edge) {
-    const int re = std::max(kMinTileRows, rows / 2);
+    const int re = std::max(1, rows / 4);
     for (int y = 0; y < ny; y += re) seg.push_back({y, std::min(ny, y + re)});
     return;
   }
@@ -663,7 +673,7 @@ extern "C" int lbm_save(lbm_domain* d, const char* path) {
   FILE* f = fopen(path, "wb");
   if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s for writing", path);
   CkptHeader h{};
-  memcpy(h.magic, "LBMCKPT2", 8);
+  memcpy(h.magic, "LBMCKPT3", 8);
   h.nx = d->P.nx;
   h.ny = d->P.ny;
   h.storage = d->P.storage;
@@ -686,7 +696,7 @@ extern "C" int lbm_load(lbm_domain* d, const char* path) {
   CkptHeader h{};
   const Layout L = layout_of(d->P);
   const size_t pb = (size_t)d->host.pstride * kPartials * sizeof(double);
-  if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "LBMCKPT2", 8) != 0 || h.nx != d->P.nx ||
+  if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "LBMCKPT3", 8) != 0 || h.nx != d->P.nx ||
       h.ny != d->P.ny || h.storage != d->P.storage || h.isothermal != d->P.isothermal ||
       h.state_bytes != L.state_bytes || h.fold_bytes != L.fold_bytes || h.part_bytes != pb) {
     fclose(f);

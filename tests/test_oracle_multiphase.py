@@ -132,3 +132,34 @@ def test_noise_is_uniform(oracle_mod):
     xs = np.array([lib.oc_noise(5, 200, x, y) for y in range(50) for x in range(200)])
     assert xs.min() >= -1.0 and xs.max() < 1.0
     assert abs(xs.mean()) < 0.02 and xs.std() == pytest.approx(1 / np.sqrt(3), rel=0.02)
+
+
+CA_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "contact_angle_0p86Tc.json")
+
+
+def test_contact_angle_table_calibrates_the_wall_density():
+    """The stored sessile-drop table (written by golden/make_contact_angle.py
+    from the oracle) falls monotonically with rho_w, and the wall density of
+    the flow-boiling workloads sits at ~60 degrees on it."""
+    import workloads as W
+
+    tab = json.load(open(CA_TABLE))["table"]
+    rw = np.array([t["rho_w"] for t in tab])
+    th = np.array([t["theta_deg"] for t in tab])
+    assert np.all(np.diff(th) <= 0) and np.all(np.diff(th[th > 0]) < 0)
+    assert th[-1] == 0.0  # complete wetting towards rho_l
+    assert np.interp(W.RHO_W_60, rw, th) == pytest.approx(60.0, abs=3.0)
+
+
+@pytest.mark.slow
+def test_contact_angle_table_reproduces(oracle_mod):
+    """One entry of the stored table, recomputed with the oracle."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location(
+        "make_ca", os.path.join(os.path.dirname(CA_TABLE), "make_contact_angle.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    ref = [t for t in json.load(open(CA_TABLE))["table"] if t["rho_w"] == 3.8][0]
+    got = mod.contact_angle(3.8)
+    assert got["theta_deg"] == pytest.approx(ref["theta_deg"], rel=1e-9)
