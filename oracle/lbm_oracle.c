@@ -15,9 +15,8 @@
  * arithmetic is IEEE double.  OpenMP only splits the per-node loops over
  * lattice rows; every reduction is a serial fixed-order loop.
  *
- * Readings of points the paper leaves silent, ambiguous or garbled are the
- * ones listed in the project design notes (R1..R31); the ones that shape the
- * code are repeated where they are used.
+ * Where the paper is silent, ambiguous or garbled, the reading taken is
+ * stated in a comment at the point where it shapes the code.
  */
 #include <math.h>
 #include <stdint.h>
@@ -100,7 +99,7 @@ static int eos_eval(const oc_params* P, double rho, double T, double* p_out,
                     double* psi_out, double* dpdT_out) {
   const double Tc = crit_T(P);
   const double kappa = 0.37464 + 1.54226 * P->omega - 0.26992 * P->omega * P->omega;
-  /* alpha(T) with sqrt(T/Tc) (reading R5 of the garbled sqrt(T/Tc^2)). */
+  /* alpha(T) with sqrt(T/Tc) (the printed sqrt(T/Tc^2) read as sqrt(T/Tc)). */
   const double s = sqrt(T / Tc);
   const double sa = 1.0 + kappa * (1.0 - s);
   const double alpha = sa * sa;
@@ -159,7 +158,7 @@ static void collide_f(const oc_params* P, const double f[9], double rho,
   }
 }
 
-/* Eq. 16 (with the relaxation sign of reading R9), Eq. 18. */
+/* Eq. 16 (relaxation read as -(g - g_eq)/tau_g: the printed sign would be unstable), Eq. 18. */
 static void collide_g(const oc_params* P, const double g[9], double T,
                       double uax, double uay, double phi, double out[9]) {
   double ge[9];
@@ -279,7 +278,7 @@ static void macro_and_forces(oc_state* S) {
   const int nx = P->nx, ny = P->ny;
   int nclamp = 0;
 
-  /* S1 moments (Eqs. 4, 6 with /rho (R1), 17) and S2 EOS. */
+  /* S1 moments (Eqs. 4, 6 with /rho, 17) and S2 EOS. */
 #pragma omp parallel for schedule(static) reduction(+ : nclamp)
   for (int y = 0; y < ny; ++y) {
     for (int x = 0; x < nx; ++x) {
@@ -326,12 +325,12 @@ static void macro_and_forces(oc_state* S) {
   S->diag[D_P_IN] = NODE(S->p, 0, ny / 2);
   S->diag[D_P_OUT] = NODE(S->p, nx - 1, ny / 2);
 
-  /* S3 forces.  Eq. 9 with psi(x1) inside the sums (R3) and G1 = 2g,
-   * G2 = g/2 (Eq. 10, R4).  Adhesion (Eq. 15): a solid neighbour enters the
+  /* S3 forces.  Eq. 9 with psi(x1) inside the sums and G1 = 2g,
+   * G2 = g/2 (Eq. 10).  Adhesion (Eq. 15): a solid neighbour enters the
    * same two sums with the pseudopotential of the false wall density,
-   * psi_w = psi(rho_w, T_wall) (R8), so that rho_w equal to the local density
+   * psi_w = psi(rho_w, T_wall), so that rho_w equal to the local density
    * exerts no net force.  Buoyancy Eq. 14 in the (rho - rho_avg) g_a form
-   * with rho_avg the mean density of the state two steps back (R7). */
+   * with rho_avg the mean density of the state two steps back. */
   const double G1 = 2.0 * P->g, G2 = 0.5 * P->g;
   const double rbar = S->rbar[1];
 #pragma omp parallel for schedule(static)
@@ -361,18 +360,18 @@ static void macro_and_forces(oc_state* S) {
       const double Fy = fsc_y + fw_y + (rho - rbar) * P->ga_y + P->fb_y;
       NODE(S->Fx, x, y) = Fx;
       NODE(S->Fy, x, y) = Fy;
-      /* S4: actual velocity, Eq. 7 with the tau_f factor read as 1 (R2). */
+      /* S4: actual velocity, Eq. 7 with the tau_f factor read as 1. */
       NODE(S->uax, x, y) = NODE(S->ux, x, y) + Fx / (2.0 * rho);
       NODE(S->uay, x, y) = NODE(S->uy, x, y) + Fy / (2.0 * rho);
     }
   }
 
-  /* S5: phase-change source, second form of Eq. 19 (R10), u = u_act, with a
-   * second-order central difference for div u (R11).  Ghost values at the
+  /* S5: phase-change source, second form of Eq. 19, u = u_act, with a
+   * second-order central difference for div u.  Ghost values at the
    * domain edge:  inlet/outlet ghost columns copy the boundary column.  At a
    * halfway bounce-back wall the two parts of phi = T div u - T (dp/dT)/(rho
    * c_v) div u use the closure consistent with the discrete transport they
-   * stand for (R11'): the T div u part cancels the conservative advection of
+   * stand for: the T div u part cancels the conservative advection of
    * the g equation, whose anti-bounce-back wall returns populations with the
    * adjacent velocity, so its ghost copies u_y of the wall-adjacent node; the
    * compression part follows the mass flux, which bounce-back makes zero at

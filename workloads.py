@@ -7,7 +7,7 @@ the method's arithmetic.  The numeric constants are inputs:
   * RHO_L, RHO_V: Maxwell coexistence densities at 0.86 Tc, omega = 0.344
     (pinned against the oracle's Maxwell construction);
   * RHO_W_60: false wall density giving a ~60 degree contact angle at
-    0.86 Tc (from the oracle's sessile-drop sweep; see the design notes).
+    0.86 Tc (from the oracle's sessile-drop sweep, tests/golden/contact_angle_0p86Tc.json).
 The workloads follow the flow-boiling channel of Sec. 2C of the paper with
 the sizes of the benchmark configurations (no dataset is involved).
 """
