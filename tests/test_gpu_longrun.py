@@ -47,7 +47,8 @@ def stats_of(samples, cfg):
                 nus.append(coef * q)
         if step in (12000, 14000):
             area[step] = int(vap.sum())
-    return {"onset": onset, "leave": leave, "area": area, "nu": float(np.mean(nus)) if nus else None}
+    return {"onset": onset, "leave": leave, "area": area, "nu": float(np.mean(nus)) if nus else None,
+            "final_finite": bool(np.isfinite(samples[-1][1]).all())}
 
 
 @pytest.fixture(scope="module")
@@ -62,38 +63,70 @@ def L():
     return lbmflow
 
 
-def test_bubble_statistics_match_oracle(L):
+@pytest.fixture(scope="module")
+def oracle_stats():
     from oracle import oracle as O
 
     cfg = W.c1()
-    print(f"case: long run 200x50, {STEPS} steps", flush=True)
-    # HIP path
-    p = L.default_params(storage=L.STORE_F32_DEV, rho_ref=W.RHO_L, T_ref=cfg.T_sat, **cfg.params())
+    Ts, rws, heat, Tn, rwn = cfg.walls()
+    o = O.Oracle(O.Params(**cfg.params()))
+    o.set_wall(0, Ts, rws, heat)
+    o.set_wall(1, Tn, rwn)
+    o.init(**cfg.init_args())
+    samples = []
+    for k in range(STEPS // K):
+        o.step(K)
+        samples.append(((k + 1) * K, o.fields()["rho"], o.diag()["heater_q"]))
+    return stats_of(samples, cfg)
+
+
+def gpu_stats(L, storage):
+    cfg = W.c1()
+    p = L.default_params(storage=storage, rho_ref=W.RHO_L, T_ref=cfg.T_sat, **cfg.params())
     d = L.Domain(p)
     Ts, rws, heat, Tn, rwn = cfg.walls()
     d.set_wall(L.SIDE_S, Ts, rws, heat)
     d.set_wall(L.SIDE_N, Tn, rwn)
     d.init(**cfg.init_args())
-    gs = []
+    samples = []
     for k in range(STEPS // K):
         d.step(K)
-        gs.append(((k + 1) * K, d.fields()["rho"], d.diag()["heater_q"]))
+        samples.append(((k + 1) * K, d.fields()["rho"], d.diag()["heater_q"]))
     d.close()
-    print("gpu done", flush=True)
-    # oracle
-    o = O.Oracle(O.Params(**cfg.params()))
-    o.set_wall(0, Ts, rws, heat)
-    o.set_wall(1, Tn, rwn)
-    o.init(**cfg.init_args())
-    os_ = []
-    for k in range(STEPS // K):
-        o.step(K)
-        os_.append(((k + 1) * K, o.fields()["rho"], o.diag()["heater_q"]))
-    g, r = stats_of(gs, cfg), stats_of(os_, cfg)
-    print("gpu", g, "\noracle", r, flush=True)
+    return stats_of(samples, cfg)
+
+
+def test_bubble_statistics_match_oracle(L, oracle_stats):
+    """FP32 deviation storage: every statistic within 2 % of the oracle."""
+    print(f"case: long run 200x50 F32_DEV, {STEPS} steps", flush=True)
+    g, r = gpu_stats(L, L.STORE_F32_DEV), oracle_stats
+    print("F32_DEV gpu", g, "\noracle", r, flush=True)
     assert r["onset"] is not None and r["leave"] is not None  # the run shows both events
     assert abs(g["onset"] - r["onset"]) <= max(K, 0.02 * r["onset"])
     assert abs(g["leave"] - r["leave"]) <= max(K, 0.02 * r["leave"])
     for t in (12000, 14000):
         assert g["area"][t] == pytest.approx(r["area"][t], rel=0.02)
     assert g["nu"] == pytest.approx(r["nu"], rel=0.02)
+
+
+def test_half_precision_long_run_statistics(L, oracle_stats):
+    """Half-precision deviation storage over the same run, against the
+    oracle.  Round-to-nearest storage of the small per-step temperature
+    increments biases the heating: FP16 nucleates about 6 % later with a
+    smaller bubble (bounds below, measured on MI355X); BF16 (8-bit
+    significand) loses the increments altogether and does not nucleate
+    within the horizon.  The BF16 run must stay finite; its statistics are
+    reported, not bounded."""
+    r = oracle_stats
+    print("case: long run 200x50 F16_DEV / BF16_DEV", flush=True)
+    g16 = gpu_stats(L, L.STORE_F16_DEV)
+    print("F16_DEV gpu", g16, flush=True)
+    assert g16["onset"] is not None and g16["leave"] is not None
+    assert abs(g16["onset"] - r["onset"]) <= 0.10 * r["onset"]
+    assert abs(g16["leave"] - r["leave"]) <= 0.05 * r["leave"]
+    for t in (12000, 14000):
+        assert g16["area"][t] == pytest.approx(r["area"][t], rel=0.25)
+    assert g16["nu"] == pytest.approx(r["nu"], rel=0.08)
+    gb = gpu_stats(L, L.STORE_BF16_DEV)
+    print("BF16_DEV gpu", gb, flush=True)
+    assert gb["final_finite"]
