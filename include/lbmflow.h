@@ -115,7 +115,10 @@ int lbm_required_bytes(const lbm_params* p, size_t* bytes);
 
 /* Create a domain on the current HIP device.  Validates p (LBM_E_INVALID):
  * nx, ny >= 3; tau_f, tau_g > 1/2; 0 < s_* < 2; c_v > 0; |u_in| < 0.1;
- * temperatures > 0.  dev_mem/dev_bytes: see Conventions. */
+ * temperatures > 0; the state buffer addressable with 32-bit offsets
+ * (11 planes of pitch x (ny + 2) elements under 2 GB: about 24 M nodes with
+ * FP32 thermal storage, 48 M with FP16/BF16).  dev_mem/dev_bytes: see
+ * Conventions. */
 int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, size_t dev_bytes,
                lbm_domain** out);
 int lbm_destroy(lbm_domain* d);
@@ -249,7 +252,9 @@ int lbm_server_destroy(lbm_server* s);
 int lbm_admission_plan(const size_t* footprints, int n, size_t cap, size_t used, int free_slots,
                        int* admit, int* n_admit);
 
-/* Plain device copy of bytes (HBM copy ceiling and counter calibration). */
+/* Plain device copy of bytes (HBM copy ceiling and counter calibration):
+ * dst, src device pointers, 16-byte aligned, bytes a multiple of 16
+ * (LBM_E_INVALID otherwise); enqueued on hip_stream. */
 int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 #ifdef __cplusplus

@@ -29,7 +29,7 @@ struct DevDomain {
   int ntiles, pad0;
   // EOS / force constants
   float a, b, R, kappa;
-  float inv_Tc, Tc, beta, c0g2;   // c0g2 = 2 / (c0 g)
+  float pad7, Tc, beta, c0g2;     // c0g2 = 2 / (c0 g)
   float G1, G2, half_1mb, pad1;    // half_1mb = (1 - beta) / 2
   // collision
   float s_e, s_eps, s_q, s_nu;

@@ -55,7 +55,6 @@ struct Codec;
 template <>
 struct Codec<LBM_STORE_F32> {
   static constexpr int E = 4;  // bytes per value
-  static __device__ __forceinline__ float ld(gptr b, uint32_t off) { return *(const float AS1*)(b + off); }
   static __device__ __forceinline__ void st(gptr_w b, uint32_t off, float v) { *(float AS1*)(b + off) = v; }
 };
 template <>
@@ -63,9 +62,6 @@ struct Codec<LBM_STORE_F32_DEV> : Codec<LBM_STORE_F32> {};
 template <>
 struct Codec<LBM_STORE_F16_DEV> {
   static constexpr int E = 2;
-  static __device__ __forceinline__ float ld(gptr b, uint32_t off) {
-    return (float)*(const _Float16 AS1*)(b + off);
-  }
   static __device__ __forceinline__ void st(gptr_w b, uint32_t off, float v) {
     v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
     *(_Float16 AS1*)(b + off) = (_Float16)v;
@@ -74,9 +70,6 @@ struct Codec<LBM_STORE_F16_DEV> {
 template <>
 struct Codec<LBM_STORE_BF16_DEV> {
   static constexpr int E = 2;
-  static __device__ __forceinline__ float ld(gptr b, uint32_t off) {
-    return __uint_as_float(((uint32_t) * (const uint16_t AS1*)(b + off)) << 16);
-  }
   static __device__ __forceinline__ void st(gptr_w b, uint32_t off, float v) {
     v = fminf(fmaxf(v, -3.3895313892515355e38f), 3.3895313892515355e38f);
     uint32_t u = __float_as_uint(v);

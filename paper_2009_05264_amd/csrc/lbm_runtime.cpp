@@ -223,7 +223,6 @@ void fill_desc(lbm_domain* d) {
   D.b = (float)p.b;
   D.R = (float)p.R;
   D.kappa = (float)kappa_of(p);
-  D.inv_Tc = (float)(1.0 / Tc);
   D.Tc = (float)Tc;
   D.beta = (float)p.beta;
   D.c0g2 = (float)(2.0 / (p.c0 * p.g));

@@ -117,3 +117,31 @@ def test_admission_plan_rejects_bad_arguments():
     na = C.c_int()
     assert lib.lbm_admission_plan(None, -1, 10, 0, 1, None, C.byref(na)) == L.LBM_E_INVALID
     assert lib.lbm_admission_plan(None, 2, 10, 0, 1, None, C.byref(na)) == L.LBM_E_INVALID
+
+
+def test_parameter_validation():
+    """lbm_required_bytes validates parameters on the host (no GPU call)."""
+    from paper_2009_05264_amd import lbmflow as L
+
+    ok = L.default_params()
+    assert L.required_bytes(ok) > 0
+    bad = [dict(nx=2), dict(ny=2), dict(tau_f=0.5), dict(tau_g=0.4), dict(c_v=0.0), dict(u_in=0.2),
+           dict(T_in=0.0), dict(storage=7), dict(bc_x=5), dict(a=0.0), dict(s_q=2.5),
+           dict(nx=16384, ny=2048, storage=L.STORE_F32_DEV)]  # beyond 32-bit state offsets
+    for kw in bad:
+        with pytest.raises(L.LbmError) as e:
+            L.required_bytes(L.default_params(**kw))
+        assert e.value.code == L.LBM_E_INVALID, kw
+    # the same size fits with half-precision storage or isothermal FP32
+    assert L.required_bytes(L.default_params(nx=16384, ny=2048, storage=L.STORE_F16_DEV)) > 0
+    assert L.required_bytes(L.default_params(nx=16384, ny=2048, storage=L.STORE_F32_DEV, isothermal=1)) > 0
+
+
+def test_required_bytes_scale_with_storage():
+    from paper_2009_05264_amd import lbmflow as L
+
+    b32 = L.required_bytes(L.default_params(nx=1024, ny=512, storage=L.STORE_F32_DEV))
+    b16 = L.required_bytes(L.default_params(nx=1024, ny=512, storage=L.STORE_F16_DEV))
+    state32 = 2 * 9 * 1024 * 512 * 8  # A/B, 9 planes of (f, g) pairs
+    assert state32 <= b32 < state32 * 1.25
+    assert b16 < b32 and b32 - b16 >= state32 // 2 * 0.99
