@@ -249,20 +249,25 @@ def main():
 
         var["serving_stream_48req"] = SS.run_stream(n=48, rate=8.0, lo=2000, hi=10000, p16=0.5, seed=5,
                                                     cap_gb=200.0, quantum=500, stream=stream)
-        # device copy ceiling (read + write bytes / time)
-        n = 1 << 28
-        a = torch.empty(n // 4, dtype=torch.float32, device="cuda")
-        c = torch.empty_like(a)
-        L.stream_copy(c.data_ptr(), a.data_ptr(), n, stream)
-        torch.cuda.synchronize()  # (events below are on the same stream)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(20):
+        # device copy ceilings (read + write bytes / time): 2 GiB arrays,
+        # far larger than the 256 MB Infinity Cache (the HBM ceiling), and
+        # 256 MiB arrays (cache-assisted)
+        for key, n in (("copy_ceiling_hbm_GBs", 2 << 30), ("copy_256MiB_GBs", 1 << 28)):
+            a = torch.zeros(n // 4, dtype=torch.float32, device="cuda")
+            c = torch.empty_like(a)
             L.stream_copy(c.data_ptr(), a.data_ptr(), n, stream)
-        e1.record()
-        torch.cuda.synchronize()
-        var["copy_ceiling_GBs"] = round(2 * n * 20 / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
-        del a, c
+            torch.cuda.synchronize()  # (events below are on the same stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                L.stream_copy(c.data_ptr(), a.data_ptr(), n, stream)
+            e1.record()
+            torch.cuda.synchronize()
+            var[key] = round(2 * n * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+            del a, c
+        hb = var.get("hbm_channel_8192x1024_f32")
+        if hb:
+            hb["frac_of_copy_ceiling"] = round(hb["achieved_GBs"] / var["copy_ceiling_hbm_GBs"], 4)
         out["variants"] = var
 
     if not args.no_cpu:
