@@ -4,7 +4,7 @@ Reads the CSV files of a kernel-trace (--kernel-trace --stats) run and of
 two counter runs (--pmc FETCH_SIZE, --pmc WRITE_SIZE) of
 paper_2009_05264_amd/profile_run.py, and writes
 
-* profiles/<name>.md: kernel statistics and the scaled HBM traffic per
+* profiles/<name>.md: kernel statistics and the scaled memory traffic per
   launch, with the commands that produced the CSV files;
 * an entry in profiles/traffic_step_kernel.json (read by bench.py): HBM
   bytes per step-kernel launch for that workload, valid for the kernel
@@ -111,12 +111,13 @@ def main():
         f"| WRITE_SIZE | {w_step:.1f} (n={nw}) | {w_copy:.1f} (n={nwc}) | {w_scale:.4f} | {wr / 1e6:.1f} MB |",
         "",
         f"Copy calibration: {args.copy_mib} MiB read and written per copy dispatch.",
-        f"HBM traffic per launch: {(rd + wr) / 1e6:.1f} MB; algorithmic bytes per launch "
+        f"Memory traffic per launch (L2 misses and write-backs, FETCH_SIZE + WRITE_SIZE; served by HBM or by "
+        f"the Infinity Cache): {(rd + wr) / 1e6:.1f} MB; algorithmic bytes per launch "
         f"{args.alg_bytes / 1e6:.1f} MB (ratio {(rd + wr) / args.alg_bytes:.3f}).",
     ]
     if step:
         lines.append(f"Kernel-trace mean duration {avg_ns / 1e3:.2f} us: algorithmic "
-                     f"{args.alg_bytes / avg_ns:.1f} GB/s, measured DRAM {(rd + wr) / avg_ns:.1f} GB/s.")
+                     f"{args.alg_bytes / avg_ns:.1f} GB/s, measured memory traffic {(rd + wr) / avg_ns:.1f} GB/s.")
     out_md = os.path.join(ROOT, "profiles", args.name + ".md")
     os.makedirs(os.path.dirname(out_md), exist_ok=True)
     open(out_md, "w").write("\n".join(lines) + "\n")
