@@ -42,7 +42,7 @@ static const double MRT_M[9][9] = {
     {0, 1, -1, 1, -1, 0, 0, 0, 0},
     {0, 0, 0, 0, 0, 1, -1, 1, -1}};
 
-enum { BCX_PERIODIC = 0, BCX_CHANNEL = 1 };
+enum { BCX_PERIODIC = 0, BCX_CHANNEL = 1, BCX_CHANNEL_P = 2 };
 enum { BCY_PERIODIC = 0, BCY_WALLS = 1 };
 enum { SIDE_S = 0, SIDE_N = 1 };
 
@@ -58,6 +58,7 @@ typedef struct {
   double U_out;              /* convective-outlet speed                      */
   double T_iso;              /* frozen temperature when isothermal           */
   double rho_mid;            /* vapour threshold for the diagnostics         */
+  double rho_out;            /* outlet density of the constant-pressure outlet */
   int32_t nx, ny;
   int32_t bc_x, bc_y;
   int32_t isothermal;        /* 1: temperature frozen at T_iso, g not evolved */
@@ -197,8 +198,10 @@ static int is_solid_row(const oc_params* P, int y) {
  *  2. source is a fluid node (periodic wrap where periodic): plain streaming;
  *  3. source is the inlet ghost column x=-1: non-equilibrium bounce-back
  *     (Zou-He) for the velocity, anti-bounce-back with the inlet state for g;
- *  4. source is the outlet ghost column x=nx: convective outlet for f, zero
- *     temperature gradient for g. */
+ *  4. source is the outlet ghost column x=nx: convective outlet for f
+ *     (BCX_CHANNEL) or non-equilibrium bounce-back at the fixed density
+ *     rho_out (BCX_CHANNEL_P, the constant-pressure exit of Sec. 2C); zero
+ *     temperature gradient for g in both. */
 static void stream_and_bc(oc_state* S) {
   const oc_params* P = &S->P;
   const int nx = P->nx, ny = P->ny;
@@ -233,7 +236,7 @@ static void stream_and_bc(oc_state* S) {
     }
   }
 
-  if (P->bc_x != BCX_CHANNEL) return;
+  if (P->bc_x == BCX_PERIODIC) return;
 
   /* Rule 3: inlet at x = 0.  Unknowns are the directions 1, 5, 8 still
    * unset after rules 1-2 (the wall rule wins at the corners). */
@@ -256,9 +259,32 @@ static void stream_and_bc(oc_state* S) {
     }
   }
 
-  /* Rule 4: convective outlet at x = nx-1, using the values at x = nx-2
-   * that rules 1-2 have just produced. */
   const int ko[3] = {3, 6, 7};
+  if (P->bc_x == BCX_CHANNEL_P) {
+    /* Rule 4, constant pressure: at x = nx-1 the populations 3, 6, 7 come
+     * from the ghost column (unless the wall rule set them).  Mass and
+     * x-momentum of the node with rho = rho_out fix the outflow speed u from
+     * the six known populations; the unknown ones then carry the known
+     * opposite ones' non-equilibrium parts (Zou and He's rule, with zero
+     * transverse velocity).  Temperature: the value at x = nx-2. */
+    for (int y = 0; y < ny; ++y) {
+      double f[9];
+      for (int i = 0; i < 9; ++i) f[i] = AT(S->f, i, nx - 1, y);
+      const double ro = P->rho_out;
+      const double u = -1.0 + (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8])) / ro;
+      if (!is_solid_row(P, y - CY[3])) AT(S->f, 3, nx - 1, y) = f[1] - 2.0 / 3.0 * ro * u;
+      if (!is_solid_row(P, y - CY[6])) AT(S->f, 6, nx - 1, y) = f[8] - 0.5 * (f[2] - f[4]) - ro * u / 6.0;
+      if (!is_solid_row(P, y - CY[7])) AT(S->f, 7, nx - 1, y) = f[5] + 0.5 * (f[2] - f[4]) - ro * u / 6.0;
+      for (int k = 0; k < 3; ++k) {
+        const int i = ko[k];
+        if (!is_solid_row(P, y - CY[i])) AT(S->g, i, nx - 1, y) = AT(S->g, i, nx - 2, y);
+      }
+    }
+    return;
+  }
+
+  /* Rule 4, convective: outlet at x = nx-1, using the values at x = nx-2
+   * that rules 1-2 have just produced. */
   for (int y = 0; y < ny; ++y) {
     for (int k = 0; k < 3; ++k) {
       const int i = ko[k];

@@ -82,11 +82,11 @@ class _CParams(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "a", "b", "R", "omega", "beta", "c0", "g", "s_nu", "s_e", "s_eps", "s_q",
         "tau_g", "c_v", "ga_x", "ga_y", "fb_x", "fb_y", "u_in", "T_in", "U_out",
-        "T_iso", "rho_mid")] + [(n, C.c_int32) for n in (
+        "T_iso", "rho_mid", "rho_out")] + [(n, C.c_int32) for n in (
         "nx", "ny", "bc_x", "bc_y", "isothermal", "single_phase")]
 
 
-BCX_PERIODIC, BCX_CHANNEL = 0, 1
+BCX_PERIODIC, BCX_CHANNEL, BCX_CHANNEL_P = 0, 1, 2
 BCY_PERIODIC, BCY_WALLS = 0, 1
 
 
@@ -124,6 +124,7 @@ class Params:
     U_out: float | None = None
     T_iso: float = 0.0
     rho_mid: float = 0.0
+    rho_out: float = 0.0     # outlet density of BCX_CHANNEL_P
     bc_x: int = BCX_CHANNEL
     bc_y: int = BCY_WALLS
     isothermal: int = 0
