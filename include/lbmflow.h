@@ -59,8 +59,12 @@ enum {
 /* Storage of the distributions in HBM.  Computation is FP32 in all cases.
  * *_DEV stores the deviation f_i - w_i rho_ref (and g_i - w_i T_ref).      */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F32_DEV = 1, LBM_STORE_F16_DEV = 2, LBM_STORE_BF16_DEV = 3 };
-/* x boundaries: periodic, or velocity inlet at x = -1/convective outlet at x = nx. */
-enum { LBM_BCX_PERIODIC = 0, LBM_BCX_CHANNEL = 1 };
+/* x boundaries: periodic; or a velocity inlet at x = -1 (non-equilibrium
+ * bounce-back for f, anti-bounce-back with the inlet state for g, Sec. 2C)
+ * with a convective outlet at x = nx (LBM_BCX_CHANNEL) or a constant-pressure
+ * outlet (LBM_BCX_CHANNEL_P: non-equilibrium bounce-back fixing the outlet
+ * density at rho_out, Sec. 2C); both outlets take zero temperature gradient. */
+enum { LBM_BCX_PERIODIC = 0, LBM_BCX_CHANNEL = 1, LBM_BCX_CHANNEL_P = 2 };
 /* y boundaries: periodic, or no-slip isothermal walls at y = -1 and y = ny. */
 enum { LBM_BCY_PERIODIC = 0, LBM_BCY_WALLS = 1 };
 enum { LBM_SIDE_S = 0, LBM_SIDE_N = 1 };
@@ -87,6 +91,7 @@ typedef struct {
   double T_iso;                  /* temperature when isothermal            */
   double rho_mid;                /* vapour threshold for diagnostics       */
   double rho_ref, T_ref;         /* reference state of *_DEV storage       */
+  double rho_out;                /* outlet density of LBM_BCX_CHANNEL_P (> 0) */
 } lbm_params;
 
 typedef struct lbm_domain lbm_domain;

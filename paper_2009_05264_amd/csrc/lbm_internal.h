@@ -39,10 +39,12 @@ struct DevDomain {
   float in_geq;                      // T_in (1 + 3 u_in^2): inlet anti-bounce-back state
   float inv_1mu;                     // 1 / (1 - u_in)
   float rho_ref, T_ref, T_iso, rho_mid;
-  float pad4[2];
+  float dro;      // rho_ref - rho_out of the constant-pressure outlet
+  float pad4;
   // buffers
   void* buf[2];         // state A/B: 9 planes [ny][pitch] of (f_i, g_i) pairs (f_i alone when isothermal)
-  float* fold[2];       // convective-outlet memory [3][ny] (deviation form), A/B
+  float* fold[2];       // convective-outlet memory [3][ny] (deviation form), A/B; unused by the
+                        // constant-pressure outlet
   const float* psiw[2]; // pseudopotential of the false wall density, S and N, [nx]
   const float* Tw[2];   // wall temperature, S and N, [nx]
   const int* heater;    // bottom heater flags [nx]

@@ -438,7 +438,7 @@ struct TileRun {
     phase = gphase ^ D.parity;
     nx = D.nx;
     ny = D.ny;
-    chan = XE && D.bc_x == LBM_BCX_CHANNEL;
+    chan = XE && D.bc_x != LBM_BCX_PERIODIC;
     walls = EDGE && D.bc_y == LBM_BCY_WALLS;
     fold = D.fold[phase];
     fold_dst = D.fold[phase ^ 1];
@@ -617,10 +617,23 @@ struct TileRun {
       if (!wN) h[8] = h[6] + d24 + rin * u * (1.f / 6.f);
     }
     if (chan && mR) {
-      // convective outlet: blend with the previous step's value
-      h[3] = (fo[0] + D.U_out * h[3]) * D.inv_1pU;
-      if (!wS) h[6] = (fo[1] + D.U_out * h[6]) * D.inv_1pU;
-      if (!wN) h[7] = (fo[2] + D.U_out * h[7]) * D.inv_1pU;
+      if (D.bc_x == LBM_BCX_CHANNEL_P) {
+        // constant-pressure outlet: non-equilibrium bounce-back at density
+        // rho_out.  The known populations give rho_out (1 + u) = f_0 + f_2 +
+        // f_4 + 2 (f_1 + f_5 + f_8); as w_0 + w_2 + w_4 + 2 (w_1 + w_5 +
+        // w_8) = 1, in deviation form rho_out u = (rho_ref - rho_out) + the
+        // same sum of h, with no cancellation when rho_out = rho_ref.
+        const float ru = D.dro + h[0] + h[2] + h[4] + 2.f * (h[1] + h[5] + h[8]);
+        const float d24 = 0.5f * (h[2] - h[4]);
+        h[3] = h[1] - (2.f / 3.f) * ru;
+        if (!wS) h[6] = h[8] - d24 - ru * (1.f / 6.f);
+        if (!wN) h[7] = h[5] + d24 - ru * (1.f / 6.f);
+      } else {
+        // convective outlet: blend with the previous step's value
+        h[3] = (fo[0] + D.U_out * h[3]) * D.inv_1pU;
+        if (!wS) h[6] = (fo[1] + D.U_out * h[6]) * D.inv_1pU;
+        if (!wN) h[7] = (fo[2] + D.U_out * h[7]) * D.inv_1pU;
+      }
     }
   }
 
@@ -983,7 +996,7 @@ __global__ void init_kernel(DevDomain D, const double* rho0, const double* T0, d
       C::st(buf, o, (float)(W[i] * (r - (double)D.rho_ref)));
       if (!D.isothermal) C::st(buf, o + C::E, (float)(W[i] * (t - (double)D.T_ref)));
     }
-    if (D.bc_x == LBM_BCX_CHANNEL && x == D.nx - 1) {
+    if (D.bc_x != LBM_BCX_PERIODIC && x == D.nx - 1) {
       D.fold[b][0 * D.ny + y] = (float)(W[3] * (r - (double)D.rho_ref));
       D.fold[b][1 * D.ny + y] = (float)(W[6] * (r - (double)D.rho_ref));
       D.fold[b][2 * D.ny + y] = (float)(W[7] * (r - (double)D.rho_ref));

@@ -82,7 +82,7 @@ int validate(const lbm_params* p) {
     return lbm_fail(LBM_E_INVALID, "nx, ny must lie in [3, 32767] (got %d x %d)", p->nx, p->ny);
   if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16_DEV)
     return lbm_fail(LBM_E_INVALID, "unknown storage %d", p->storage);
-  if ((p->bc_x != LBM_BCX_PERIODIC && p->bc_x != LBM_BCX_CHANNEL) ||
+  if ((p->bc_x != LBM_BCX_PERIODIC && p->bc_x != LBM_BCX_CHANNEL && p->bc_x != LBM_BCX_CHANNEL_P) ||
       (p->bc_y != LBM_BCY_PERIODIC && p->bc_y != LBM_BCY_WALLS))
     return lbm_fail(LBM_E_INVALID, "unknown boundary kind");
   if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5))
@@ -97,8 +97,10 @@ int validate(const lbm_params* p) {
     return lbm_fail(LBM_E_INVALID, "temperatures must be positive");
   if (!(p->a > 0) || !(p->b > 0) || !(p->R > 0) || !(p->c0 > 0) || p->g == 0)
     return lbm_fail(LBM_E_INVALID, "EOS constants out of range");
-  if (p->bc_x == LBM_BCX_CHANNEL && p->nx < 3)
+  if (p->bc_x != LBM_BCX_PERIODIC && p->nx < 3)
     return lbm_fail(LBM_E_INVALID, "a channel needs nx >= 3");
+  if (p->bc_x == LBM_BCX_CHANNEL_P && !(p->rho_out > 0))
+    return lbm_fail(LBM_E_INVALID, "a constant-pressure outlet needs rho_out > 0");
   {
     // The kernels address a state buffer with 32-bit byte offsets: 9 planes
     // plus the two-plane base shift of the boundary pull must stay below 2 GB.
@@ -188,7 +190,9 @@ extern "C" int lbm_params_default(lbm_params* p) {
   p->T_in = 0.95 * Ts;
   p->U_out = -1.0;
   p->T_iso = Ts;
+  // saturated densities at 0.86 Tc (Maxwell construction of these constants)
   p->rho_mid = 0.5 * (6.4989457632878835 + 0.3796789993997205);
+  p->rho_out = 6.4989457632878835;
   p->rho_ref = 0.0;
   p->T_ref = 0.0;
   return LBM_OK;
@@ -250,6 +254,7 @@ void fill_desc(lbm_domain* d) {
   D.T_ref = (float)p.T_ref;
   D.T_iso = (float)p.T_iso;
   D.rho_mid = (float)p.rho_mid;
+  D.dro = (float)(p.rho_ref - p.rho_out);
 }
 
 }  // namespace

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbmflow.so")
 LBM_OK = 0
 LBM_E_INVALID, LBM_E_NOMEM, LBM_E_CAP, LBM_E_DEVICE, LBM_E_NAN, LBM_E_STATE = -1, -2, -3, -4, -5, -6
 STORE_F32, STORE_F32_DEV, STORE_F16_DEV, STORE_BF16_DEV = 0, 1, 2, 3
-BCX_PERIODIC, BCX_CHANNEL = 0, 1
+BCX_PERIODIC, BCX_CHANNEL, BCX_CHANNEL_P = 0, 1, 2
 BCY_PERIODIC, BCY_WALLS = 0, 1
 SIDE_S, SIDE_N = 0, 1
 
@@ -36,7 +36,7 @@ class Params(C.Structure):
         (n, C.c_double) for n in (
             "a", "b", "R", "omega", "beta", "c0", "g", "tau_f", "s_e", "s_eps", "s_q",
             "tau_g", "c_v", "ga_x", "ga_y", "fb_x", "fb_y", "u_in", "T_in", "U_out",
-            "T_iso", "rho_mid", "rho_ref", "T_ref")]
+            "T_iso", "rho_mid", "rho_ref", "T_ref", "rho_out")]
 
 
 class Diag(C.Structure):

@@ -38,9 +38,12 @@ def test_binding_struct_sizes():
     from paper_2009_05264_amd import lbmflow as L
 
     txt = open(HEADER).read()
-    assert C.sizeof(L.Params) == 8 * 4 + 24 * 8
+    assert C.sizeof(L.Params) == 8 * 4 + 25 * 8
     assert C.sizeof(L.Diag) == 8 + 8 * 8
     assert "double rho_ref, T_ref;" in txt
+    # rho_out is the last member of lbm_params
+    assert txt.index("double rho_out;") > txt.index("double rho_ref, T_ref;")
+    assert txt.index("double rho_out;") < txt.index("} lbm_params;")
 
 
 def test_binding_names_match_header():
@@ -127,11 +130,13 @@ def test_parameter_validation():
     assert L.required_bytes(ok) > 0
     bad = [dict(nx=2), dict(ny=2), dict(tau_f=0.5), dict(tau_g=0.4), dict(c_v=0.0), dict(u_in=0.2),
            dict(T_in=0.0), dict(storage=7), dict(bc_x=5), dict(a=0.0), dict(s_q=2.5),
+           dict(bc_x=L.BCX_CHANNEL_P, rho_out=0.0),
            dict(nx=16384, ny=2048, storage=L.STORE_F32_DEV)]  # beyond 32-bit state offsets
     for kw in bad:
         with pytest.raises(L.LbmError) as e:
             L.required_bytes(L.default_params(**kw))
         assert e.value.code == L.LBM_E_INVALID, kw
+    assert L.required_bytes(L.default_params(bc_x=L.BCX_CHANNEL_P)) > 0  # default rho_out = rho_l
     # the same size fits with half-precision storage or isothermal FP32
     assert L.required_bytes(L.default_params(nx=16384, ny=2048, storage=L.STORE_F16_DEV)) > 0
     assert L.required_bytes(L.default_params(nx=16384, ny=2048, storage=L.STORE_F32_DEV, isothermal=1)) > 0

@@ -113,6 +113,9 @@ def test_channel_diagnostics(L):
     (121, 9, 1, 1),    # channel, 3 strips with a 1-column last strip
     (3, 4, 1, 1),      # smallest channel
     (61, 70, 1, 0),    # channel periodic in y, several row segments
+    (121, 9, 2, 1),    # constant-pressure exit, walls
+    (3, 4, 2, 1),      # smallest channel with the pressure exit
+    (61, 70, 2, 0),    # pressure exit, periodic in y
 ])
 def test_shapes_and_boundaries(L, nx, ny, bcx, bcy):
     """Ragged tiles and every boundary combination, 40 steps, with a liquid
@@ -123,15 +126,29 @@ def test_shapes_and_boundaries(L, nx, ny, bcx, bcy):
     r0 = np.where((x - nx / 3) ** 2 + (y - ny / 2) ** 2 < (min(nx, ny) / 3) ** 2, W.RHO_V, W.RHO_L)
     r0 = r0 * (1 + 1e-3 * np.sin(x + 2 * y))
     init = dict(rho0=r0, T_u=cfg.T_sat)
-    d, o = run_pair(L, cfg, 40, init=init, bc_x=bcx, bc_y=bcy, rows=8)
+    extra = dict(rho_out=W.RHO_L) if bcx == 2 else {}
+    d, o = run_pair(L, cfg, 40, init=init, bc_x=bcx, bc_y=bcy, rows=8, **extra)
     e = rel_errors(d.fields(), o.fields())
     print(e)
     assert e["rho"] < 2e-5 and e["T"] < 2e-5 and e["u"] < 5e-5, e
 
 
+@pytest.mark.parametrize("rho_out_frac", [1.0, 0.97])
+def test_pressure_outlet_channel_100_steps(L, rho_out_frac):
+    """The 200x50 channel with the constant-pressure exit (Sec. 2C) at
+    rho_out = rho_l, and at 0.97 rho_l (outflow driven by the exit pressure,
+    rho_out differing from the storage reference density)."""
+    print(f"case: pressure-exit channel 200x50 rho_out={rho_out_frac} rho_l", flush=True)
+    d, o = run_pair(L, W.c1(), 100, bc_x=2, rho_out=rho_out_frac * W.RHO_L)
+    e = rel_errors(d.fields(), o.fields())
+    print(e)
+    assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
+
+
 def test_isothermal_and_single_phase_flags(L):
     cfg = W.Channel(nx=90, ny=20, heater_len=10)
-    for over in (dict(isothermal=1), dict(single_phase=1, fb_x=1e-6, ga_y=0.0)):
+    for over in (dict(isothermal=1), dict(single_phase=1, fb_x=1e-6, ga_y=0.0),
+                 dict(isothermal=1, bc_x=2, rho_out=W.RHO_L)):
         print(f"case: flags {over}", flush=True)
         d, o = run_pair(L, cfg, 50, **over)
         e = rel_errors(d.fields(), o.fields())
