@@ -266,8 +266,22 @@ static void stream_and_bc(oc_state* S) {
      * x-momentum of the node with rho = rho_out fix the outflow speed u from
      * the six known populations; the unknown ones then carry the known
      * opposite ones' non-equilibrium parts (Zou and He's rule, with zero
-     * transverse velocity).  Temperature: the value at x = nx-2. */
+     * transverse velocity).  Temperature: the value at x = nx-2.
+     * The paper gives no corner rule.  Next to a wall the completion would
+     * mix the wall's bounce-back values into the outflow speed; in the
+     * multiphase channel that loop grows until the run fails (~15k steps at
+     * 40 x 250 and 40 x 1000).  There the unknown populations take their
+     * values at x = nx-2 instead (zero gradient, as for the temperature). */
     for (int y = 0; y < ny; ++y) {
+      if (is_solid_row(P, y - 1) || is_solid_row(P, y + 1)) {
+        for (int k = 0; k < 3; ++k) {
+          const int i = ko[k];
+          if (is_solid_row(P, y - CY[i])) continue;
+          AT(S->f, i, nx - 1, y) = AT(S->f, i, nx - 2, y);
+          AT(S->g, i, nx - 1, y) = AT(S->g, i, nx - 2, y);
+        }
+        continue;
+      }
       double f[9];
       for (int i = 0; i < 9; ++i) f[i] = AT(S->f, i, nx - 1, y);
       const double ro = P->rho_out;

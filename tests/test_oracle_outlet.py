@@ -74,3 +74,47 @@ def test_hagen_poiseuille_with_pressure_outlet(oracle_mod):
     assert (p1 - p0) / (x1 - x0) == pytest.approx(dpdx_theory, rel=0.01)
     # the exit holds rho_out on the rows away from the walls
     assert np.abs(rho[1:-1, -1] - rho_out).max() < 1e-12
+
+
+def test_pressure_exit_corners_take_zero_gradient(oracle_mod):
+    """Outlet nodes next to a wall: the populations from the ghost column
+    equal those at x = nx-2 (zero gradient), the wall's own ones stay."""
+    O = oracle_mod
+    Ts = _ts(O)
+    rl, rv, _ = O.maxwell(Ts)
+    P = O.Params(nx=20, ny=12, bc_x=O.BCX_CHANNEL_P, bc_y=O.BCY_WALLS, rho_out=rl, T_in=0.95 * Ts,
+                 T_iso=Ts, rho_mid=0.5 * (rl + rv), u_in=0.01)
+    o = O.Oracle(P)
+    o.set_wall(0, Ts, 3.8)
+    o.set_wall(1, Ts, 3.8)
+    o.init(rho_u=rl, T_u=Ts, noise=0.05, seed=5)
+    o.step(2)
+    f, g = o.streamed()
+    for y, ghost in ((0, (3, 7)), (P.ny - 1, (3, 6))):
+        for i in ghost:
+            assert f[i, y, -1] == f[i, y, -2] and g[i, y, -1] == g[i, y, -2]
+
+
+def test_pressure_exit_channel_stays_bounded(oracle_mod):
+    """Regression for the corner rule: the multiphase channel of the paper's
+    cross-section (40 rows, Re_in = 0.96, T_in = 0.9 Tc, exit at rho_l),
+    40 x 250, 20000 steps.  With the Zou-He completion also applied next to
+    the walls, the corner velocity grows from ~0.05 and the run fails near
+    step 16500."""
+    O = oracle_mod
+    Tc = O.crit_temperature()
+    Tin = 0.9 * Tc
+    rl, rv, _ = O.maxwell(Tin)
+    nx, ny = 250, 40
+    P = O.Params(nx=nx, ny=ny, bc_x=O.BCX_CHANNEL_P, bc_y=O.BCY_WALLS, rho_out=rl, u_in=0.96 / 6.0 / ny,
+                 T_in=Tin, T_iso=Tin, rho_mid=0.5 * (rl + rv))
+    o = O.Oracle(P)
+    rw = rv + 0.6 * (rl - rv)
+    o.set_wall(0, np.full(nx, Tin), np.full(nx, rw))
+    o.set_wall(1, np.full(nx, Tin), np.full(nx, rw))
+    o.init(rho_u=rl, T_u=Tin, noise=1e-3, seed=11)
+    o.step(20000)
+    F = o.fields()
+    assert np.isfinite(F["rho"]).all() and np.isfinite(F["T"]).all()
+    assert max(np.abs(F["ux"]).max(), np.abs(F["uy"]).max()) < 0.08
+    assert F["T"].min() > 0.85 * Tc
