@@ -618,16 +618,20 @@ struct TileRun {
     }
     if (chan && mR) {
       if (D.bc_x == LBM_BCX_CHANNEL_P) {
-        // constant-pressure outlet: non-equilibrium bounce-back at density
+        // Constant-pressure outlet: non-equilibrium bounce-back at density
         // rho_out.  The known populations give rho_out (1 + u) = f_0 + f_2 +
         // f_4 + 2 (f_1 + f_5 + f_8); as w_0 + w_2 + w_4 + 2 (w_1 + w_5 +
         // w_8) = 1, in deviation form rho_out u = (rho_ref - rho_out) + the
-        // same sum of h, with no cancellation when rho_out = rho_ref.
-        const float ru = D.dro + h[0] + h[2] + h[4] + 2.f * (h[1] + h[5] + h[8]);
-        const float d24 = 0.5f * (h[2] - h[4]);
-        h[3] = h[1] - (2.f / 3.f) * ru;
-        if (!wS) h[6] = h[8] - d24 - ru * (1.f / 6.f);
-        if (!wN) h[7] = h[5] + d24 - ru * (1.f / 6.f);
+        // same sum of h, with no cancellation when rho_out = rho_ref.  Next
+        // to a wall the redirected pulls already hold the populations of
+        // x = nx-2 (zero gradient), which is the corner rule.
+        if (!wS && !wN) {
+          const float ru = D.dro + h[0] + h[2] + h[4] + 2.f * (h[1] + h[5] + h[8]);
+          const float d24 = 0.5f * (h[2] - h[4]);
+          h[3] = h[1] - (2.f / 3.f) * ru;
+          h[6] = h[8] - d24 - ru * (1.f / 6.f);
+          h[7] = h[5] + d24 - ru * (1.f / 6.f);
+        }
       } else {
         // convective outlet: blend with the previous step's value
         h[3] = (fo[0] + D.U_out * h[3]) * D.inv_1pU;

