@@ -159,11 +159,11 @@ def main():
                      "kernel": "step_kernel", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(1e6 * launch_s, 3),
                      "rocprof_kernel_us": None if prof is None else round(prof["kernel_trace_avg_us"], 3),
-                     "note": "avg_launch_us: HIP events on the kernels' stream around the timed graph "
-                             "replay divided by the launches, i.e. kernel execution plus the dispatch gap "
-                             "between dependent launches (about 2.5 us here); rocprof_kernel_us is the "
-                             "kernel-trace execution time of the committed profile. The 1600x200 FP32 A/B "
-                             "state (46 MB) fits the 256 MB Infinity Cache"},
+                     "note": "avg_launch_us: HIP events on the kernels' stream around the timed replay "
+                             "of 32-launch graphs divided by the launches, i.e. kernel execution plus any "
+                             "gap between dependent launches; rocprof_kernel_us is the kernel-trace "
+                             "execution time of the committed profile. The 1600x200 FP32 A/B state "
+                             "(46 MB) fits the 256 MB Infinity Cache"},
         "health": {"nonfinite": diag["nonfinite"], "psi_clamped": diag["psi_clamped"]},
     }
 

@@ -32,17 +32,20 @@ void lbm_drop_graphs(lbm_domain* d) {
   d->graphs.clear();
 }
 
-// Two launches (phase 0 then phase 1) captured once and replayed: the
+// Launch pairs (phase 0 then phase 1) captured once and replayed: the
 // kernels take everything that changes from step to step from device memory.
-static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int), void* ctx) {
+static int capture_pairs(hipStream_t s, GraphEntry* g, int pairs, int (*enqueue)(void*, int), void* ctx) {
   HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  int rc0 = enqueue(ctx, 0);
-  int rc1 = rc0 ? rc0 : enqueue(ctx, 1);
+  int rc = 0;
+  for (int q = 0; q < pairs && !rc; ++q) {
+    rc = enqueue(ctx, 0);
+    if (!rc) rc = enqueue(ctx, 1);
+  }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s, &graph);
-  if (rc0 || rc1) {
+  if (rc) {
     if (graph) (void)hipGraphDestroy(graph);
-    return rc0 ? rc0 : rc1;
+    return rc;
   }
   if (e != hipSuccess) return lbm_fail(LBM_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
   hipGraphExec_t exec = nullptr;
@@ -53,6 +56,43 @@ static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int)
   }
   g->graph = graph;
   g->exec = exec;
+  return LBM_OK;
+}
+
+static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int), void* ctx) {
+  return capture_pairs(s, g, 1, enqueue, ctx);
+}
+
+// Steps per long replay graph.  One hipGraphLaunch costs the host a few
+// microseconds, more than a step of a small domain: replaying two launches
+// per graph left a ~2.5 us gap per step on a 1600x200 channel, a graph of
+// 32 launches none.
+constexpr int kLongPairs = 16;
+
+// Replays up to n steps from an even step: long graphs, then pair graphs
+// (captured on first use); *done counts the steps enqueued, and the at most
+// one step left over is the caller's.
+static int replay_steps(hipStream_t s, GraphEntry* pair, GraphEntry* lng, int64_t n,
+                        int (*enqueue)(void*, int), void* ctx, int64_t* done) {
+  *done = 0;
+  const int64_t nl = n / (2 * kLongPairs);
+  if (nl > 0) {
+    if (!lng->exec) {
+      int rc = capture_pairs(s, lng, kLongPairs, enqueue, ctx);
+      if (rc) return rc;
+    }
+    for (int64_t k = 0; k < nl; ++k) HIPCHECK(hipGraphLaunch(lng->exec, s));
+    *done += nl * 2 * kLongPairs;
+  }
+  const int64_t np = (n - *done) / 2;
+  if (np > 0) {
+    if (!pair->exec) {
+      int rc = capture_pair(s, pair, enqueue, ctx);
+      if (rc) return rc;
+    }
+    for (int64_t k = 0; k < np; ++k) HIPCHECK(hipGraphLaunch(pair->exec, s));
+    *done += 2 * np;
+  }
   return LBM_OK;
 }
 
@@ -70,16 +110,12 @@ int lbm_run_steps(lbm_domain* d, int64_t n) {
     if (rc) return rc;
     --n;
   }
-  if (d->graphs.empty()) {
-    GraphEntry g;
-    int rc = capture_pair(d->stream, &g, enqueue_domain_phase, d);
-    if (rc) return rc;
-    d->graphs.push_back(g);
-  }
-  const int64_t pairs = n / 2;
-  for (int64_t k = 0; k < pairs; ++k) HIPCHECK(hipGraphLaunch(d->graphs[0].exec, d->stream));
-  d->step += 2 * pairs;
-  if (n & 1) return lbm_enqueue_steps(d, 1);
+  if (d->graphs.size() < 2) d->graphs.resize(2);
+  int64_t done = 0;
+  int rc = replay_steps(d->stream, &d->graphs[0], &d->graphs[1], n, enqueue_domain_phase, d, &done);
+  d->step += done;
+  if (rc) return rc;
+  if (n > done) return lbm_enqueue_steps(d, n - done);
   return LBM_OK;
 }
 
@@ -97,7 +133,8 @@ struct lbm_batch {
     int nfins = 0;
   };
   std::vector<Group> groups;
-  GraphEntry graph;
+  GraphEntry graph;       // one launch pair
+  GraphEntry graph_long;  // kLongPairs launch pairs
   int64_t k = 0;  // steps done by the batch
   int rows = kDefaultTileRows;
 };
@@ -140,9 +177,11 @@ static int enqueue_batch_phase(void* ctx, int phase) {
 }
 
 static void drop_batch_graph(lbm_batch* b) {
-  if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
-  if (b->graph.graph) (void)hipGraphDestroy(b->graph.graph);
-  b->graph = GraphEntry{};
+  for (GraphEntry* g : {&b->graph, &b->graph_long}) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    *g = GraphEntry{};
+  }
 }
 
 // Retile every domain (rows per tile) keeping the pending reductions.
@@ -294,15 +333,12 @@ extern "C" int lbm_batch_step(lbm_batch* b, int64_t n) {
     if (rc) return rc;
     --n;
   }
-  if (!b->graph.exec) {
-    int rc = capture_pair(b->stream, &b->graph, enqueue_batch_phase, b);
-    if (rc) return rc;
-  }
-  const int64_t pairs = n / 2;
-  for (int64_t i = 0; i < pairs; ++i) HIPCHECK(hipGraphLaunch(b->graph.exec, b->stream));
-  b->k += 2 * pairs;
-  for (lbm_domain* d : b->doms) d->step += 2 * pairs;
-  if (n & 1) return batch_steps_plain(b, 1);
+  int64_t done = 0;
+  int rc = replay_steps(b->stream, &b->graph, &b->graph_long, n, enqueue_batch_phase, b, &done);
+  b->k += done;
+  for (lbm_domain* d : b->doms) d->step += done;
+  if (rc) return rc;
+  if (n > done) return batch_steps_plain(b, n - done);
   return LBM_OK;
 }
 

@@ -39,7 +39,7 @@ struct lbm_domain {
   int64_t step = 0;
   bool inited = false;
   bool in_batch = false;
-  std::vector<GraphEntry> graphs;  // [0]: two-step replay graph of this domain
+  std::vector<GraphEntry> graphs;  // replay graphs of this domain: [0] two steps, [1] 32 steps
 };
 
 int lbm_fail(int code, const char* fmt, ...);

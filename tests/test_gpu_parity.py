@@ -173,18 +173,20 @@ def test_tiling_invariance_bitwise(L):
 
 
 def test_repeatable_and_graph_equals_plain(L):
-    """Same run twice is bitwise identical; 20 steps through the replayed
-    graph equal 20 single launches."""
+    """Same run twice is bitwise identical; 75 steps through the replayed
+    graphs (32-step and 2-step graphs, a single launch, from an odd start as
+    well) equal 75 single launches."""
     cfg = W.c1()
     out = []
-    for split in ((20,), (1,) * 20, (20,)):
+    for split in ((75,), (1,) * 75, (75,), (1, 33, 9, 32)):
         d = make_gpu(L, cfg)
         d.init(**cfg.init_args())
         for n in split:
             d.step(n)
         out.append(d.fields())
     for k in out[0]:
-        assert np.array_equal(out[0][k], out[1][k]) and np.array_equal(out[0][k], out[2][k]), k
+        for o in out[1:]:
+            assert np.array_equal(out[0][k], o[k]), k
 
 
 def test_checkpoint_resume_bitwise(L, tmp_path):
@@ -237,7 +239,7 @@ def test_batch_equals_solo(L):
         doms.append(d)
     doms[1].step(0)
     b = L.Batch(doms)
-    b.step(40)
+    b.step(40)  # one 32-step graph, four pairs
     b.sync()
     b.close()
     for s, d in zip(solo, doms):
