@@ -144,7 +144,10 @@ int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, const doubl
 int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_uniform,
                     double T_uniform, double noise_rel, uint64_t seed);
 
-/* Enqueue nsteps time steps on the domain's stream (nsteps >= 0). */
+/* Enqueue nsteps time steps on the domain's stream (nsteps >= 0): one
+ * kernel launch per step; from 8 steps on, replayed from captured hipGraphs
+ * of 32 and of 2 launches (captured on first use, dropped when the tiling
+ * changes).  Results are bitwise the same however nsteps is split. */
 int lbm_step(lbm_domain* d, int64_t nsteps);
 int lbm_sync(lbm_domain* d);
 int64_t lbm_step_count(const lbm_domain* d);
@@ -175,7 +178,7 @@ int lbm_set_tile_rows(lbm_domain* d, int rows);
 
 /* Batched execution: n domains (all created on the same device, stepped
  * together, one launch per step over the concatenated tile table, replayed
- * from a captured hipGraph).  tune_cache_json: NULL = no autotuning (each
+ * from captured hipGraphs as in lbm_step).  tune_cache_json: NULL = no autotuning (each
  * domain keeps its own tiles), "" = autotune on the batch without a cache
  * file, otherwise a text file the autotuner reads and appends to. */
 int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune_cache_json, lbm_batch** out);
