@@ -260,6 +260,18 @@ def test_channel_1600x200_parity(L):
     assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
 
 
+def test_hbm_resident_channel_parity(L):
+    """The 8192x1024 channel of the HBM measurement (18 574 tiles, about nine
+    rounds of resident waves, every XCD with a long contiguous tile run), 6
+    steps against the oracle on every node."""
+    cfg = W.roofline_channel()
+    print("case: channel 8192x1024 6 steps", flush=True)
+    d, o = run_pair(L, cfg, 6)
+    e = rel_errors(d.fields(), o.fields())
+    print(e, flush=True)
+    assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
+
+
 @pytest.mark.parametrize("storage,tol", [("F16_DEV", 3e-3), ("BF16_DEV", 3e-2)])
 def test_half_precision_storage_error(L, storage, tol):
     """Precision study: FP16/BF16 deviation storage against the FP64 oracle
