@@ -150,3 +150,22 @@ def test_required_bytes_scale_with_storage():
     state32 = 2 * 9 * 1024 * 512 * 8  # A/B, 9 planes of (f, g) pairs
     assert state32 <= b32 < state32 * 1.25
     assert b16 < b32 and b32 - b16 >= state32 // 2 * 0.99
+
+
+def _build_c_example(out):
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pkg = os.path.join(os.path.dirname(HEADER), "..", "paper_2009_05264_amd")
+    src = os.path.join(pkg, "examples", "channel.c")
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Werror", src, "-I", os.path.dirname(HEADER), "-L", pkg,
+           "-llbmflow", "-Wl,-rpath," + os.path.abspath(pkg), "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return out
+
+
+def test_c_example_builds_against_the_header(tmp_path):
+    """The C example uses only include/lbmflow.h and links against the library."""
+    assert os.path.exists(_build_c_example(tmp_path / "channel"))
