@@ -272,6 +272,26 @@ def test_hbm_resident_channel_parity(L):
     assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
 
 
+def test_near_maximum_size_parity(L):
+    """8192 x 2880 FP32 thermal channel (23.6 M nodes): the 9-plane state,
+    with the two-plane base shift of the boundary pulls, sits just under the
+    2 GB reach of 32-bit byte offsets (the limit lbm_create enforces).  3
+    steps against the oracle on every node."""
+    import psutil
+
+    if psutil.virtual_memory().available < 24 * 2**30:
+        pytest.skip("needs ~12 GB of host memory for the oracle")
+    cfg = W.Channel(nx=8192, ny=2880, heater_len=1150, steps=3)
+    p = L.default_params(storage=L.STORE_F32_DEV, rho_ref=W.RHO_L, T_ref=cfg.T_sat, **cfg.params())
+    assert 11 * 8192 * (2880 + 2) * 8 > 0.95 * (2**31 - 2**24)  # within 5 % of the limit
+    assert L.required_bytes(p) > 0
+    print("case: channel 8192x2880 3 steps", flush=True)
+    d, o = run_pair(L, cfg, 3)
+    e = rel_errors(d.fields(), o.fields())
+    print(e, flush=True)
+    assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
+
+
 @pytest.mark.parametrize("storage,tol", [("F16_DEV", 3e-3), ("BF16_DEV", 3e-2)])
 def test_half_precision_storage_error(L, storage, tol):
     """Precision study: FP16/BF16 deviation storage against the FP64 oracle
