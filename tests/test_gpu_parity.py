@@ -335,3 +335,46 @@ def test_pressure_exit_paper_cross_section_long_run(L):
     e = rel_errors(g, r)
     print(e, flush=True)
     assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
+
+
+def test_autotuner_and_cache(L, tmp_path):
+    """The batch autotuner times rows-per-tile x grid configurations with real
+    steps and writes its choice to the cache; the tuned batch still equals
+    the domains stepped alone (bitwise), and a second batch of the same shape
+    reads the cache instead of tuning."""
+    cfgs = [W.Channel(nx=130, ny=30, heater_len=10, seed=5), W.Channel(nx=250, ny=41, heater_len=16, seed=6)]
+    cache = tmp_path / "tune.txt"
+
+    def fresh():
+        out = []
+        for c in cfgs:
+            d = make_gpu(L, c)
+            d.init(**c.init_args())
+            out.append(d)
+        return out
+
+    print("case: autotuner with cache file", flush=True)
+    doms = fresh()
+    b = L.Batch(doms, tune_cache=str(cache))
+    tuned = doms[0].steps
+    assert tuned > 0 and all(d.steps == tuned for d in doms)  # tuning steps are real steps
+    b.step(40)
+    b.sync()
+    b.close()
+    lines = cache.read_text().split()
+    assert len(lines) == 3 and lines[0].startswith("v2_n2_")
+    assert int(lines[1]) in (4, 6, 8, 12) and int(lines[2]) in (0, 8, 16)
+    for c, d in zip(cfgs, doms):
+        s = make_gpu(L, c)
+        s.init(**c.init_args())
+        s.step(tuned + 40)
+        fs, fd = s.fields(), d.fields()
+        for k in fs:
+            assert np.array_equal(fs[k], fd[k]), k
+    doms2 = fresh()
+    b2 = L.Batch(doms2, tune_cache=str(cache))
+    assert all(d.steps == 0 for d in doms2)  # read from the cache, no tuning steps
+    b2.step(10)
+    b2.sync()
+    b2.close()
+    assert cache.read_text().split() == lines
