@@ -378,3 +378,39 @@ def test_autotuner_and_cache(L, tmp_path):
     b2.sync()
     b2.close()
     assert cache.read_text().split() == lines
+
+
+def test_caller_memory_and_device_readout(L):
+    """A domain in caller-supplied device memory steps bitwise like one the
+    library allocates; the device read-out writes the same float32 fields
+    into caller tensors; a buffer below lbm_required_bytes is rejected."""
+    import torch
+
+    cfg = W.Channel(nx=130, ny=30, heater_len=10, seed=9)
+    p = L.default_params(storage=L.STORE_F32_DEV, rho_ref=W.RHO_L, T_ref=cfg.T_sat, **cfg.params())
+    need = L.required_bytes(p)
+    print(f"case: caller memory {need} bytes", flush=True)
+    with pytest.raises(L.LbmError) as e:
+        L.Domain(p, device_buffer=torch.empty(need - 256, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == L.LBM_E_INVALID
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    outs = []
+    for dev in (buf, None):
+        d = L.Domain(p, device_buffer=dev)
+        Ts, rws, heat, Tn, rwn = cfg.walls()
+        d.set_wall(L.SIDE_S, Ts, rws, heat)
+        d.set_wall(L.SIDE_N, Tn, rwn)
+        d.init(**cfg.init_args())
+        d.step(50)
+        outs.append((d, d.fields()))
+    for k in outs[0][1]:
+        assert np.array_equal(outs[0][1][k], outs[1][1][k]), k
+    d, f = outs[1]
+    t = {k: torch.full((cfg.ny, cfg.nx), float("nan"), dtype=torch.float32, device="cuda")
+         for k in ("rho", "ux", "uy", "T")}
+    d.fields_device(t["rho"], t["ux"], t["uy"], t["T"])
+    torch.cuda.synchronize()
+    for k in t:
+        assert np.array_equal(t[k].cpu().numpy().astype(np.float64), f[k]), k
+    for dd, _ in outs:
+        dd.close()
