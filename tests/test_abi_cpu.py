@@ -169,3 +169,20 @@ def _build_c_example(out):
 def test_c_example_builds_against_the_header(tmp_path):
     """The C example uses only include/lbmflow.h and links against the library."""
     assert os.path.exists(_build_c_example(tmp_path / "channel"))
+
+
+def test_library_maxwell_matches_oracle():
+    """lbm_maxwell (host, in the library) against the oracle's independent
+    equal-area construction, 0.6-0.95 Tc, both acentric factors used here."""
+    import workloads as W
+    from oracle import oracle as O
+    from paper_2009_05264_amd import lbmflow as L
+
+    for omega in (0.344, 0.32):
+        p = L.default_params(omega=omega)
+        for frac in (0.6, 0.7, 0.8, 0.86, 0.9, 0.95):
+            T = frac * W.TC
+            rl, rv, ps = L.maxwell(p, T)
+            ol, ov, ops = O.maxwell(T, omega=omega)
+            assert rl == pytest.approx(ol, rel=1e-8) and rv == pytest.approx(ov, rel=1e-8)
+            assert ps == pytest.approx(ops, rel=1e-8)
