@@ -921,8 +921,10 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return k * q + min(k, rem) + i;
 }
 
-// Row buffers of interior tiles (look-ahead kDepthInterior - 1 rows).
-constexpr int kDepthInterior = 3;
+// Row buffers of interior tiles (look-ahead kDepthInterior - 1 rows).  Two,
+// as on boundary tiles: deeper look-ahead (3 or 4 buffers) measured slower
+// on both the cache-resident and the HBM-resident channel.
+constexpr int kDepthInterior = 2;
 
 template <int S, int MODE>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel(
