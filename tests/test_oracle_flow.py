@@ -254,3 +254,37 @@ def test_channel_runs_clean(oracle_mod):
     d = o.diag()
     assert d["nonfinite"] == 0 and d["psi_clamped"] == 0
     assert d["heater_q"] > 0
+
+
+def test_phase_change_source_adiabatic_response(oracle_mod):
+    """Eq. 19 (second form) with the T div u correction of the conservative
+    g transport: in a uniform fluid set in a weak compressive/expansive
+    motion u_x = U sin(kx), the temperature responds as the first law of a
+    compressible fluid gives, dT/dt = -T (dp/dT)_rho / (rho c_v) div u
+    (heat conduction negligible at this wavelength and horizon).  Liquid and
+    vapour densities, two values of c_v; amplitude within 2 %."""
+    O = oracle_mod
+    Ts = _ts(O)
+    rl, rv, _ = O.maxwell(Ts)
+    L, ny, U, n = 256, 3, 1e-3, 10
+    k = 2 * np.pi / L
+    x = np.arange(L)
+    ux = U * np.sin(k * x)
+    for rho0, cv in ((rl, 6.0), (rl, 12.0), (rv, 6.0)):
+        P = O.Params(nx=L, ny=ny, bc_x=O.BCX_PERIODIC, bc_y=O.BCY_PERIODIC, single_phase=1, ga_y=0.0,
+                     T_in=Ts, T_iso=Ts, c_v=cv)
+        o = O.Oracle(P)
+        o.init(rho_u=rho0, T_u=Ts)
+        fs = np.zeros((9, ny, L))
+        gs = np.zeros((9, ny, L))
+        for xi in range(L):
+            fs[:, :, xi] = O.feq(rho0, ux[xi], 0.0)[:, None]
+            gs[:, :, xi] = (O.W * Ts * (1 + 3 * O.CX * ux[xi]))[:, None]
+        o.set_state(fs, gs)
+        T0 = o.fields()["T"][1]
+        o.step(n)
+        dT = o.fields()["T"][1] - T0
+        _, _, dpdT, _ = O.eos(P, rho0, Ts)
+        amp = np.sum(dT * np.cos(k * x)) / np.sum(np.cos(k * x) ** 2)
+        expected = -n * Ts * dpdT / (rho0 * cv) * U * k
+        assert amp == pytest.approx(expected, rel=0.02), (rho0, cv, amp, expected)
