@@ -288,3 +288,21 @@ def test_phase_change_source_adiabatic_response(oracle_mod):
         amp = np.sum(dT * np.cos(k * x)) / np.sum(np.cos(k * x) ** 2)
         expected = -n * Ts * dpdT / (rho0 * cv) * U * k
         assert amp == pytest.approx(expected, rel=0.02), (rho0, cv, amp, expected)
+
+
+def test_channel_ends_settle_to_a_uniform_stream(oracle_mod):
+    """A channel without walls (periodic in y) fed by the velocity inlet and
+    drained by the convective outlet: a uniform stream at u_in is an exact
+    steady state of the pair, and the start-up transient from rest decays
+    to it (rho uniform to 1e-12, u = u_in to 1e-12 after 5000 steps)."""
+    O = oracle_mod
+    Ts = _ts(O)
+    u = 0.01
+    P = O.Params(nx=40, ny=5, bc_x=O.BCX_CHANNEL, bc_y=O.BCY_PERIODIC, single_phase=1, isothermal=1,
+                 ga_y=0.0, T_in=Ts, T_iso=Ts, u_in=u)
+    o = O.Oracle(P)
+    o.init(rho_u=1.0, T_u=Ts)
+    o.step(5000)
+    F = o.fields()
+    assert F["rho"].max() - F["rho"].min() < 1e-12
+    assert np.abs(F["ux"] - u).max() < 1e-12 and np.abs(F["uy"]).max() < 1e-12
