@@ -102,7 +102,9 @@ typedef struct {
   int64_t step;        /* state index (number of completed steps)          */
   double mass;         /* sum rho                                          */
   double energy;       /* sum T                                            */
-  double heater_q;     /* sum over heater cells of 2 (T_wall - T(x, 0))     */
+  double heater_q;     /* sum over heater cells of 2 (T_wall - T(x, 0)):    */
+                       /* the wall heat flux behind the Nusselt number      */
+                       /* and delta T* of Sec. 3B                           */
   double vapor_cells;  /* number of nodes with rho < rho_mid               */
   double psi_clamped;  /* nodes where p - rho/3 > 0 made psi imaginary     */
   double nonfinite;    /* nodes with non-finite rho or T                   */
@@ -137,15 +139,16 @@ int lbm_destroy(lbm_domain* d);
 int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, const double* rho_w,
                       const int32_t* heater);
 
-/* Initial state: post-collision f = f^eq(rho0, 0), g = w_i T0 at every node,
+/* Initial state (Sec. 2C starts the channel from saturated liquid at rest):
+ * post-collision f = f^eq(rho0, 0), g = w_i T0 at every node,
  * with rho0 = the array, or rho_uniform (1 + noise_rel * xi(x, y)) where xi
  * in [-1, 1) is the SplitMix64 variate of seed ^ (y nx + x); T0 = the array
  * or T_uniform.  Resets the step counter and the lagged mean density. */
 int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_uniform,
                     double T_uniform, double noise_rel, uint64_t seed);
 
-/* Enqueue nsteps time steps on the domain's stream (nsteps >= 0): one
- * kernel launch per step; from 8 steps on, replayed from captured hipGraphs
+/* Enqueue nsteps time steps (the update of Sec. 2 summarised at the top of
+ * this file) on the domain's stream (nsteps >= 0): one kernel launch per step; from 8 steps on, replayed from captured hipGraphs
  * of 32 and of 2 launches (captured on first use, dropped when the tiling
  * changes).  Results are bitwise the same however nsteps is split. */
 int lbm_step(lbm_domain* d, int64_t nsteps);
@@ -158,7 +161,9 @@ int lbm_read_fields(lbm_domain* d, double* rho, double* ux, double* uy, double* 
 /* Same fields into caller device buffers of nx*ny floats (no host copy). */
 int lbm_read_fields_device(lbm_domain* d, float* rho, float* ux, float* uy, float* T);
 
-/* Diagnostics of the current state. */
+/* Diagnostics of the current state (FP64 sums of the lbm_diag fields; the
+ * vapour count uses rho < rho_mid, the phase test of the departure
+ * statistics of Sec. 3B). */
 int lbm_read_diag(lbm_domain* d, lbm_diag* out);
 /* Per-step diagnostics recorded on the device by lbm_step (ring of the last
  * capacity states, oldest first).  *n receives the number written. */
@@ -168,7 +173,10 @@ int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n);
 int lbm_save(lbm_domain* d, const char* path);
 int lbm_load(lbm_domain* d, const char* path);
 
-/* Maxwell equal-area coexistence of the Peng-Robinson EOS of p at T < Tc. */
+/* Maxwell equal-area coexistence of the Peng-Robinson EOS of p at T < Tc
+ * (the construction of Sec. 2D, Fig. 4b): saturated liquid and vapour
+ * densities and the saturation pressure (host FP64; LBM_E_INVALID outside
+ * 0 < T < Tc). */
 int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double* rho_v, double* p_sat);
 
 /* Rows per tile of the step kernel: 0 selects the automatic choice (4 or 8
