@@ -73,7 +73,14 @@ struct Tile {
   DevDomain* d;
   int x0, y0, y1;
   int local;  // tile index within its domain (partials slot); 0 = first tile
+  // code path, chosen on the host so that a wave branches on its tile record
+  // alone: bits 0-1 when stepping, bits 2-3 for read-out (kTileInterior,
+  // kTileRowEdge, kTileColumnEdge); kTileIsothermal when the domain is
+  int kind;
+  int pad;
 };
+
+enum TileKind { kTileInterior = 0, kTileRowEdge = 1, kTileColumnEdge = 2, kTileIsothermal = 16 };
 
 enum StepMode { MODE_STEP = 0, MODE_READOUT = 1 };
 

@@ -346,6 +346,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
 // Fixed-order sum of tiles [t0, t1) of SoA partial sums by one wave; every
 // lane gets the result.  Loads are issued four tiles at a time per lane.
 __device__ __forceinline__ void sum_partials(const double* parts, int stride, int t0, int t1,
@@ -400,7 +406,8 @@ struct TileRun {
   Rsrc rs, rd;
   int pitch, sst[9];  // plane byte offsets
   int kb;             // extra base offset of the pull resource (column-edge tiles)
-  float gbar;
+  float gbar;     // rho_ref - mean density (formed in run(), first used by stage 2)
+  double mpart;   // this lane's level-1 mass slice
   int r_end;
   // boundary tiles: -1 in lanes whose column is 0 (mL) / nx-1 (mR)
   int mL = 0, mR = 0;
@@ -460,11 +467,10 @@ struct TileRun {
     kb = XE && TH ? 2 * sst[1] : 0;
     rs = make_rsrc((const char*)D.buf[phase] - kb - (pitch + 1) * E2);
     rd = make_rsrc(D.buf[phase ^ 1]);
-    // mean density two states back: sum of the level-1 slices written by the
-    // previous launch's finalizers
-    double mass = lane < kFin ? D.l1[phase][lane * kPartials + P_MASS] : 0.0;
-    mass = wave_sum(mass);
-    gbar = (float)((double)D.rho_ref - mass / ((double)nx * (double)ny));
+    // mean density two states back: the level-1 slices written by the
+    // previous launch's finalizers, summed in run() once the first rows are
+    // in flight
+    mpart = lane < kFin ? D.l1[phase][lane * kPartials + P_MASS] : 0.0;
     r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) bh[i] = bk[i] = ck[i] = fc[i] = 0.f;
@@ -861,14 +867,22 @@ struct TileRun {
     if constexpr (NB >= 4) fetch<2>(y0);
     iter<false, false, false, true, 0>(y0 - 2);
     iter<false, false, false, true, 1 % NB>(y0 - 1);
+    gbar = (float)((double)D.rho_ref - wave_sum(mpart) / ((double)nx * (double)ny));
     iter<true, false, false, true, 2 % NB>(y0);
     iter<true, true, false, true, 3 % NB>(y0 + 1);
     steady<4 % NB>(y0 + 2);
-    // tile partial sums (fixed order: lane tree)
-    double v[kPartials] = {acc_mass, acc_energy, acc_q, (double)acc_vap, (double)acc_clamp,
-                           (double)acc_nf, acc_pin, acc_pout};
-#pragma unroll
-    for (int q = 0; q < kPartials; ++q) v[q] = wave_sum(v[q]);
+    // tile partial sums: FP64 in a fixed order (lane tree), the counts as
+    // exact 32-bit integers; heater and pressure sums are zero off the edge
+    // tiles (fewer cross-lane rounds at the end of every tile)
+    double v[kPartials];
+    v[P_MASS] = wave_sum(acc_mass);
+    v[P_ENERGY] = wave_sum(acc_energy);
+    v[P_VAPOR] = (double)wave_sum_int(acc_vap);
+    v[P_CLAMP] = (double)wave_sum_int(acc_clamp);
+    v[P_NONFINITE] = (double)wave_sum_int(acc_nf);
+    v[P_HEATQ] = EDGE ? wave_sum(acc_q) : 0.0;
+    v[P_PIN] = EDGE ? wave_sum(acc_pin) : 0.0;
+    v[P_POUT] = EDGE ? wave_sum(acc_pout) : 0.0;
     if (lane == 0) {
       double* out = (MODE == MODE_STEP ? D.partials[phase] : D.readout_partials) + tl.local;
 #pragma unroll
@@ -942,17 +956,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
   for (int b = blockIdx.x - skip; b < ntiles; b += nb) {
     const int t = xcd_tile(b, ntiles);
     const Tile AS4& tl = ((const Tile AS4*)tiles)[t];
-    DRef D = *(const DevDomain AS4*)tl.d;
-    const int r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
-    const bool xin = tl.x0 >= 3 && tl.x0 + kWave - 2 < D.nx;
-    const bool yin = tl.y0 - 2 >= 1 && r_end <= D.ny - 2;
-    if (D.isothermal) {
-      if (!xin) TileRun<S, MODE, 2, false, 2>(tl, gphase).run();
-      else if (!yin) TileRun<S, MODE, 1, false, 2>(tl, gphase).run();
+    // the path comes with the tile record: no descriptor load before the branch
+    const int kind = tl.kind;
+    const int k = MODE == MODE_STEP ? (kind & 3) : ((kind >> 2) & 3);
+    if (kind & kTileIsothermal) {
+      if (k == kTileColumnEdge) TileRun<S, MODE, 2, false, 2>(tl, gphase).run();
+      else if (k == kTileRowEdge) TileRun<S, MODE, 1, false, 2>(tl, gphase).run();
       else TileRun<S, MODE, 0, false, kDepthInterior>(tl, gphase).run();
     } else {
-      if (!xin) TileRun<S, MODE, 2, true, 2>(tl, gphase).run();
-      else if (!yin) TileRun<S, MODE, 1, true, 2>(tl, gphase).run();
+      if (k == kTileColumnEdge) TileRun<S, MODE, 2, true, 2>(tl, gphase).run();
+      else if (k == kTileRowEdge) TileRun<S, MODE, 1, true, 2>(tl, gphase).run();
       else TileRun<S, MODE, 0, true, kDepthInterior>(tl, gphase).run();
     }
   }

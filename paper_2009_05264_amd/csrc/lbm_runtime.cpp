@@ -304,7 +304,8 @@ int lbm_build_tiles(lbm_domain* d) {
   std::vector<std::pair<int, int>> seg;
   for (int t = 0; t < strips; ++t) {
     const int x0 = t * kStripInterior;
-    // same test as the kernel's choice of the column-edge path
+    // A strip whose 64 lanes reach column 0, 1 or 2, or column nx-1 or
+    // beyond, takes the column-edge path (inlet, outlet or periodic seam).
     const bool column_edge = !(x0 >= 3 && x0 + kWave - 2 < nx);
     strip_segments(ny, rows, column_edge, seg);
     for (const auto& sg : seg) {
@@ -313,6 +314,15 @@ int lbm_build_tiles(lbm_domain* d) {
       tl.x0 = x0;
       tl.y0 = sg.first;
       tl.y1 = sg.second;
+      // Otherwise a tile whose pulled rows (y0-2 .. r_end, r_end = y1+1 when
+      // stepping, y1 for read-out) reach row 0 or ny-1 takes the row-edge path.
+      auto kind = [&](int r_end) {
+        return column_edge ? kTileColumnEdge
+               : (tl.y0 - 2 >= 1 && r_end <= ny - 2) ? kTileInterior
+                                                      : kTileRowEdge;
+      };
+      tl.kind = kind(tl.y1 + 1) | kind(tl.y1) << 2 | (d->P.isothermal ? kTileIsothermal : 0);
+      tl.pad = 0;
       d->tiles_h.push_back(tl);
     }
   }
