@@ -23,12 +23,13 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & HBM GB/s (coupled D2Q9+T step); batched MLUPS, p50/p99 solve time"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {0: 144, 1: 144, 2: 72, 3: 72}  # 18 values read + 18 written, once each
-KERNEL_SRC = os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_kernels.hip")
+# the step kernel and the host code that shapes its tiles
+KERNEL_SRC = [os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_kernels.hip"), os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_runtime.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRC)).hexdigest()[:16]
 
 
 def profile_entry(workload: str, storage: str):

@@ -259,24 +259,15 @@ void fill_desc(lbm_domain* d) {
 
 }  // namespace
 
-// Rows per tile (automatic).  A tile's march spends four extra row steps
-// filling its pipeline, so short tiles trade redundant pulls for
-// parallelism: 8 rows (pull overhead 1.5x) unless that leaves fewer than
-// about 512 tiles, then 4.
-int lbm_auto_rows(int nx, int ny) {
-  const int strips = (nx + kStripInterior - 1) / kStripInterior;
-  return (long long)strips * ((ny + 7) / 8) >= 512 ? 8 : 4;
-}
-
 // Row segments [y0, y1) of one strip.  Tiles that run the boundary path do
 // more work per row, so they get fewer rows: strips that reach column 0 or
-// nx - 1 are cut in chunks of rows / 4 (at least one row); the other strips get a 3-row head
-// and tail (the rows within two of a wall or of the periodic seam) and
-// near-equal chunks of about `rows` in between.
+// nx - 1 are cut in chunks of (rows + 1) / 4 rows (at least one); the other
+// strips get a 3-row head and tail (the rows within two of a wall or of the
+// periodic seam) and near-equal chunks of about `rows` in between.
 static void strip_segments(int ny, int rows, bool column_edge, std::vector<std::pair<int, int>>& seg) {
   seg.clear();
   if (column_edge) {
-    const int re = std::max(1, rows / 4);
+    const int re = std::max(1, (rows + 1) / 4);
     for (int y = 0; y < ny; y += re) seg.push_back({y, std::min(ny, y + re)});
     return;
   }
@@ -295,18 +286,44 @@ static void strip_segments(int ny, int rows, bool column_edge, std::vector<std::
   if (t > 0) seg.push_back({ny - t, ny});
 }
 
+// A strip whose 64 lanes reach column 0, 1 or 2, or column nx-1 or beyond,
+// takes the column-edge path (inlet, outlet or periodic seam).
+static bool strip_is_column_edge(int x0, int nx) { return !(x0 >= 3 && x0 + kWave - 2 < nx); }
+
+static long long tile_count(int nx, int ny, int rows) {
+  const int strips = (nx + kStripInterior - 1) / kStripInterior;
+  std::vector<std::pair<int, int>> seg;
+  long long n = 0;
+  for (int t = 0; t < strips; ++t) {
+    strip_segments(ny, rows, strip_is_column_edge(t * kStripInterior, nx), seg);
+    n += (long long)seg.size();
+  }
+  return n;
+}
+
+// Rows per tile (automatic).  A tile's march spends four extra row steps
+// filling its pipeline, and one wave runs it from start to end, so a step
+// of a domain whose tiles all run at once lasts about one tile chain: take
+// the shortest tiles (4 to 8 rows) whose waves, with the finalizer waves,
+// fit on the SIMDs at once.  Larger domains run in several rounds, bound by
+// memory traffic, where 7 rows measured best with FP32 storage (1-4 % ahead
+// of 8 from 1600x400 to 8192x2048) and 8 rows with 16-bit storage.
+int lbm_auto_rows(int nx, int ny, int simds, bool half) {
+  for (int r = 4; r < 8; ++r)
+    if (tile_count(nx, ny, r) + kFin <= simds) return r;
+  return half ? 8 : 7;
+}
+
 int lbm_build_tiles(lbm_domain* d) {
   lbm_drop_graphs(d);
   const int nx = d->P.nx, ny = d->P.ny;
-  const int rows = d->rows > 0 ? std::max(kMinTileRows, d->rows) : lbm_auto_rows(nx, ny);
+  const int rows = d->rows > 0 ? std::max(kMinTileRows, d->rows) : lbm_auto_rows(nx, ny, d->simds, elem_bytes(d->P.storage) == 2);
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
   d->tiles_h.clear();
   std::vector<std::pair<int, int>> seg;
   for (int t = 0; t < strips; ++t) {
     const int x0 = t * kStripInterior;
-    // A strip whose 64 lanes reach column 0, 1 or 2, or column nx-1 or
-    // beyond, takes the column-edge path (inlet, outlet or periodic seam).
-    const bool column_edge = !(x0 >= 3 && x0 + kWave - 2 < nx);
+    const bool column_edge = strip_is_column_edge(x0, nx);
     strip_segments(ny, rows, column_edge, seg);
     for (const auto& sg : seg) {
       Tile tl;
@@ -361,6 +378,13 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   if (!d) return lbm_fail(LBM_E_NOMEM, "host allocation failed");
   d->P = *p;
   d->rows = 0;  // automatic
+  {
+    // SIMDs of the current device (four per compute unit), for the tile shape
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      d->simds = 4 * cus;
+  }
   if (hip_stream) {
     d->stream = (hipStream_t)hip_stream;
     d->own_stream = false;

@@ -31,6 +31,7 @@ struct lbm_domain {
   int ntiles = 0;
   int rows = kDefaultTileRows;
   int grid = 0;  // 0: one workgroup per tile
+  int simds = 1024;  // SIMDs of the device (automatic tile rows)
   float* psiw_d[2] = {nullptr, nullptr};
   float* Tw_d[2] = {nullptr, nullptr};
   int* heater_d = nullptr;

@@ -30,12 +30,13 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SRC = os.path.join(HERE, "csrc", "lbm_kernels.hip")
+# the step kernel and the host code that shapes its tiles
+KERNEL_SRC = [os.path.join(HERE, "csrc", "lbm_kernels.hip"), os.path.join(HERE, "csrc", "lbm_runtime.cpp")]
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRC)).hexdigest()[:16]
 
 
 def _one(dirname: str, suffix: str) -> str:
@@ -93,7 +94,7 @@ def main():
     avg_ns = step[0][2] if step else float("nan")
 
     lines = [f"# step_kernel, workload {args.workload}, storage {args.storage}", "",
-             f"kernel source sha256[:16]: `{kernel_sha()}`", ""]
+             f"kernel and tiling source sha256[:16]: `{kernel_sha()}`", ""]
     if args.kt_cmd:
         lines += ["Kernel trace command:", "", "```", args.kt_cmd, "```", ""]
     lines += ["| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
