@@ -262,7 +262,7 @@ static int autotune(lbm_batch* b, const char* cache) {
       }
     }
   }
-  const int row_opts[] = {4, 6, 8, 12};
+  const int row_opts[] = {4, 6, 7, 8, 12};
   const int grid_opts[] = {0, 8, 16};
   float best = 1e30f;
   int brow = kDefaultTileRows, bgrid = 0;
