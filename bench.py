@@ -24,7 +24,7 @@ METRIC = "MLUPS & HBM GB/s (coupled D2Q9+T step); batched MLUPS, p50/p99 solve t
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {0: 144, 1: 144, 2: 72, 3: 72}  # 18 values read + 18 written, once each
 # the step kernel and the host code that shapes its tiles
-KERNEL_SRC = [os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_kernels.hip"), os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_runtime.cpp")]
+KERNEL_SRC = [os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_kernels.hip"), os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_tiles.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
 
 

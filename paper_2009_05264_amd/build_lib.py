@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmflow.so")
-SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_batch.cpp", "lbm_server.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_runtime.cpp", "lbm_tiles.cpp", "lbm_batch.cpp", "lbm_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

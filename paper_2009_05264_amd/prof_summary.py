@@ -31,7 +31,7 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 # the step kernel and the host code that shapes its tiles
-KERNEL_SRC = [os.path.join(HERE, "csrc", "lbm_kernels.hip"), os.path.join(HERE, "csrc", "lbm_runtime.cpp")]
+KERNEL_SRC = [os.path.join(HERE, "csrc", "lbm_kernels.hip"), os.path.join(HERE, "csrc", "lbm_tiles.cpp")]
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
 
 
