@@ -157,10 +157,13 @@ def test_isothermal_and_single_phase_flags(L):
 
 def test_tiling_invariance_bitwise(L):
     """Per-node arithmetic does not depend on the tile shape: fields after 30
-    steps are bitwise equal for every rows-per-tile setting."""
+    steps are bitwise equal for every rows-per-tile setting, the automatic
+    one (None) included; 7, 11 and 15 rows cut the column-edge strips into
+    chunks of (rows + 1) / 4, one row more than rows / 4."""
     cfg = W.c1()
     ref = None
-    for rows in (4, 8, 17, 32, 64):
+    for rows in (4, None, 5, 7, 8, 11, 15, 17, 32, 64):
+        print(f"case: c1 rows {rows}", flush=True)
         d = make_gpu(L, cfg, rows=rows)
         d.init(**cfg.init_args())
         d.step(30)
@@ -170,6 +173,26 @@ def test_tiling_invariance_bitwise(L):
         else:
             for k in f:
                 assert np.array_equal(f[k], ref[k]), (rows, k)
+
+
+def test_tiling_invariance_ragged_bitwise(L):
+    """The same on a ragged channel (253x37: a partial last strip, uneven row
+    chunks) with a periodic variant, automatic and explicit tile heights."""
+    for bc_x in (L.BCX_CHANNEL, L.BCX_PERIODIC):
+        cfg = W.Channel(nx=253, ny=37, heater_len=14)
+        ref = None
+        for rows in (None, 5, 6, 7, 11):
+            print(f"case: 253x37 bc_x {bc_x} rows {rows}", flush=True)
+            d = make_gpu(L, cfg, rows=rows, bc_x=bc_x)
+            d.init(**cfg.init_args())
+            d.step(30)
+            f = d.fields()
+            d.close()
+            if ref is None:
+                ref = f
+            else:
+                for k in f:
+                    assert np.array_equal(f[k], ref[k]), (bc_x, rows, k)
 
 
 def test_repeatable_and_graph_equals_plain(L):
