@@ -179,9 +179,12 @@ int lbm_load(lbm_domain* d, const char* path);
  * 0 < T < Tc). */
 int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double* rho_v, double* p_sat);
 
-/* Rows per tile of the step kernel: 0 selects the automatic choice (4 or 8
- * rows by domain size); values below 2 act as 2.  Results do not depend on
- * it (bitwise). */
+/* Rows per tile of the step kernel: 0 selects the automatic choice (the
+ * shortest tiles of 4 to 7 rows whose waves all fit on the device's SIMDs at
+ * once; otherwise 7 rows with FP32 storage, 8 with FP16/BF16); values below
+ * 2 act as 2.  Results do not depend on it (bitwise).  Synchronises the
+ * domain's stream (the pending partial sums move to the new tiling) and
+ * drops its replay graphs. */
 int lbm_set_tile_rows(lbm_domain* d, int rows);
 
 /* Batched execution: n domains (all created on the same device, stepped
