@@ -96,6 +96,8 @@ template <int S>
 struct BufIO;
 template <>
 struct BufIO<LBM_STORE_F32> {
+  static constexpr bool kRaw = false;  // as PairIO
+  static __device__ __forceinline__ float unpack(float w) { return w; }
   template <int IMM>
   static __device__ __forceinline__ float ld(Rsrc r, int voff, int soff) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * 4, soff, 0));
@@ -110,11 +112,18 @@ struct BufIO<LBM_STORE_F32_DEV> : BufIO<LBM_STORE_F32> {};
 // Thermal domains store f_i and g_i of a node side by side (one 8-byte or
 // 4-byte pair), so one load or store moves both distributions of a
 // direction.  IMM is an offset in pairs.
+//
+// kRaw: the 16-bit formats load the packed bits into the prefetch registers
+// (f holds the word, g is left alone) and unpack() converts them when the
+// row is consumed.  Converting at load time would make the loop wait, before
+// its back-edge, for the row it has just prefetched.
 template <int S>
 struct PairIO;
 template <>
 struct PairIO<LBM_STORE_F32> {
   static constexpr int E2 = 8;
+  static constexpr bool kRaw = false;
+  static __device__ __forceinline__ void unpack(float, float&, float&) {}
   template <int IMM>
   static __device__ __forceinline__ void ld(Rsrc r, int voff, int soff, float& f, float& g) {
     const unsigned long long w =
@@ -138,9 +147,13 @@ struct PairIO<LBM_STORE_F32_DEV> : PairIO<LBM_STORE_F32> {};
 template <>
 struct PairIO<LBM_STORE_F16_DEV> {
   static constexpr int E2 = 4;
+  static constexpr bool kRaw = true;
   template <int IMM>
   static __device__ __forceinline__ void ld(Rsrc r, int voff, int soff, float& f, float& g) {
-    const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * E2, soff, 0);
+    f = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * E2, soff, 0));
+  }
+  static __device__ __forceinline__ void unpack(float w, float& f, float& g) {
+    const uint32_t u = __float_as_uint(w);
     f = (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xFFFFu));
     g = (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
   }
@@ -155,9 +168,13 @@ struct PairIO<LBM_STORE_F16_DEV> {
 template <>
 struct PairIO<LBM_STORE_BF16_DEV> {
   static constexpr int E2 = 4;
+  static constexpr bool kRaw = true;
   template <int IMM>
   static __device__ __forceinline__ void ld(Rsrc r, int voff, int soff, float& f, float& g) {
-    const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * E2, soff, 0);
+    f = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * E2, soff, 0));
+  }
+  static __device__ __forceinline__ void unpack(float w, float& f, float& g) {
+    const uint32_t u = __float_as_uint(w);
     f = __uint_as_float(u << 16);
     g = __uint_as_float(u & 0xFFFF0000u);
   }
@@ -173,10 +190,13 @@ struct PairIO<LBM_STORE_BF16_DEV> {
 };
 template <>
 struct BufIO<LBM_STORE_F16_DEV> {
+  static constexpr bool kRaw = true;
   template <int IMM>
   static __device__ __forceinline__ float ld(Rsrc r, int voff, int soff) {
-    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, voff + IMM * 2, soff, 0);
-    return (float)__builtin_bit_cast(_Float16, u);
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff + IMM * 2, soff, 0));
+  }
+  static __device__ __forceinline__ float unpack(float w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)__float_as_uint(w));
   }
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
     v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
@@ -185,11 +205,12 @@ struct BufIO<LBM_STORE_F16_DEV> {
 };
 template <>
 struct BufIO<LBM_STORE_BF16_DEV> {
+  static constexpr bool kRaw = true;
   template <int IMM>
   static __device__ __forceinline__ float ld(Rsrc r, int voff, int soff) {
-    const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, voff + IMM * 2, soff, 0);
-    return __uint_as_float(((uint32_t)u) << 16);
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff + IMM * 2, soff, 0));
   }
+  static __device__ __forceinline__ float unpack(float w) { return __uint_as_float(__float_as_uint(w) << 16); }
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
     v = fminf(fmaxf(v, -3.3895313892515355e38f), 3.3895313892515355e38f);
     uint32_t u = __float_as_uint(v);
@@ -658,6 +679,19 @@ struct TileRun {
     // ---------------- stage 1: row r
     sa = walls && (r < 0 || r >= ny);
     if (PF) fetch<(B + NB - 1) % NB>(r + NB - 1);
+    // 16-bit storage: convert the row's packed words now (see PairIO)
+    float uh[9], uk[9];
+    if constexpr (TH ? PairIO<S>::kRaw : BufIO<S>::kRaw) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        if constexpr (TH)
+          PairIO<S>::unpack(ph[B][i], uh[i], uk[i]);
+        else
+          uh[i] = BufIO<S>::unpack(ph[B][i]);
+      }
+      ah = uh;
+      if constexpr (TH) ak = uk;
+    }
     int fo_off = kDrop;  // outlet memory store of this row
     if (sa) {
       const float psiW = r < 0 ? psiS : psiN;
