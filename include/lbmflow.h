@@ -189,12 +189,19 @@ int lbm_set_tile_rows(lbm_domain* d, int rows);
 
 /* Batched execution: n domains (all created on the same device, stepped
  * together, one launch per step over the concatenated tile table, replayed
- * from captured hipGraphs as in lbm_step).  tune_cache_json: NULL = no autotuning (each
- * domain keeps its own tiles), "" = autotune on the batch without a cache
- * file, otherwise a text file the autotuner reads and appends to. */
+ * from captured hipGraphs as in lbm_step).  tune_cache_json: NULL = no autotuning:
+ * domains on automatic rows (lbm_set_tile_rows 0) get one tile height chosen
+ * for the batch's combined tiles (fewest rounds of waves on the SIMDs times
+ * the row steps of a tile), and their own choice back when the batch is
+ * destroyed; "" = autotune on the batch without a cache file,
+ * otherwise a text file the autotuner reads and appends to.  Results do not
+ * depend on the choice (bitwise). */
 int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune_cache_json, lbm_batch** out);
 int lbm_batch_step(lbm_batch* b, int64_t nsteps);
 int lbm_batch_sync(lbm_batch* b);
+/* Synchronises the batch's stream and hands its domains back for stepping
+ * alone (a domain retiled for the batch gets its own rows back; a device
+ * error from that is returned after the batch is freed). */
 int lbm_batch_destroy(lbm_batch* b);
 
 /* ---------------------------------------------------------------- serving

@@ -184,6 +184,45 @@ static void drop_batch_graph(lbm_batch* b) {
   }
 }
 
+// Without the autotuner, the domains on automatic rows get one tile height
+// chosen for the batch as a whole.  Each domain alone picks its rows for its
+// own tiles only, and the combined launch may then queue several tile
+// chains on a SIMD.  A step of a batch that is not bound by memory traffic
+// lasts about (rounds of waves on the SIMDs) x (row steps of a chain,
+// rows + 4): the height (4 to 8 rows) that minimises this product is taken,
+// ties going to the taller tiles (fewer halo rows).  The choice is undone by
+// lbm_batch_destroy.
+static int batch_auto_rows(lbm_batch* b) {
+  if (b->doms.size() < 2) return LBM_OK;
+  bool any = false;
+  for (lbm_domain* d : b->doms) any = any || d->rows == 0;
+  if (!any) return LBM_OK;
+  const long long simds = b->doms[0]->simds;
+  int pick = 8;
+  long long best = -1;
+  for (int r = 4; r <= 8; ++r) {
+    long long waves = 0;
+    for (lbm_domain* d : b->doms)
+      waves += (d->rows == 0 ? lbm_tile_count(d->P.nx, d->P.ny, r) : d->ntiles) + kFin;
+    const long long cost = (waves + simds - 1) / simds * (r + 4);
+    if (best < 0 || cost <= best) {
+      best = cost;
+      pick = r;
+    }
+  }
+  for (lbm_domain* d : b->doms) {
+    if (d->rows != 0) continue;
+    d->batch_rows = pick;
+    d->in_batch = false;
+    int rc = lbm_set_tile_rows(d, 0);
+    d->in_batch = true;
+    if (rc) return rc;
+    d->host.parity = (int)((d->step - b->k) & 1);
+    HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
+  }
+  return build_groups(b);
+}
+
 // Retile every domain (rows per tile) keeping the pending reductions.
 static int retile(lbm_batch* b, int rows) {
   for (lbm_domain* d : b->doms) {
@@ -316,6 +355,7 @@ extern "C" int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune
   }
   int rc = build_groups(b);
   if (!rc && tune_cache_json) rc = autotune(b, tune_cache_json[0] ? tune_cache_json : nullptr);
+  else if (!rc) rc = batch_auto_rows(b);
   if (rc) {
     lbm_batch_destroy(b);
     return rc;
@@ -356,11 +396,18 @@ extern "C" int lbm_batch_destroy(lbm_batch* b) {
     if (g.tiles_d) (void)hipFree(g.tiles_d);
     if (g.fins_d) (void)hipFree(g.fins_d);
   }
+  int rc = LBM_OK;
   for (lbm_domain* d : b->doms) {
     d->in_batch = false;
     d->host.parity = 0;
     (void)hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice);
+    if (d->batch_rows) {
+      // back to the domain's own automatic rows (pending sums carried over)
+      d->batch_rows = 0;
+      const int r = lbm_set_tile_rows(d, d->rows);
+      if (r && rc == LBM_OK) rc = r;
+    }
   }
   delete b;
-  return LBM_OK;
+  return rc;
 }

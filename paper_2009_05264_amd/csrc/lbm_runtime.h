@@ -32,6 +32,7 @@ struct lbm_domain {
   int rows = kDefaultTileRows;
   int grid = 0;  // 0: one workgroup per tile
   int simds = 1024;  // SIMDs of the device (automatic tile rows)
+  int batch_rows = 0;  // automatic rows chosen for the batch the domain is in (0: its own choice)
   float* psiw_d[2] = {nullptr, nullptr};
   float* Tw_d[2] = {nullptr, nullptr};
   int* heater_d = nullptr;
@@ -45,6 +46,7 @@ struct lbm_domain {
 
 int lbm_fail(int code, const char* fmt, ...);
 int lbm_build_tiles(lbm_domain* d);
+long long lbm_tile_count(int nx, int ny, int rows);  // tiles lbm_build_tiles makes at that height
 int lbm_enqueue_steps(lbm_domain* d, int64_t n);
 int lbm_run_steps(lbm_domain* d, int64_t n);
 void lbm_drop_graphs(lbm_domain* d);

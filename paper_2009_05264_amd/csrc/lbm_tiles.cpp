@@ -52,7 +52,7 @@ static void strip_segments(int ny, int rows, bool column_edge, std::vector<std::
 // takes the column-edge path (inlet, outlet or periodic seam).
 static bool strip_is_column_edge(int x0, int nx) { return !(x0 >= 3 && x0 + kWave - 2 < nx); }
 
-static long long tile_count(int nx, int ny, int rows) {
+long long lbm_tile_count(int nx, int ny, int rows) {
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
   std::vector<std::pair<int, int>> seg;
   long long n = 0;
@@ -72,14 +72,17 @@ static long long tile_count(int nx, int ny, int rows) {
 // of 8 from 1600x400 to 8192x2048) and 8 rows with 16-bit storage.
 static int lbm_auto_rows(int nx, int ny, int simds, bool half) {
   for (int r = 4; r < 8; ++r)
-    if (tile_count(nx, ny, r) + kFin <= simds) return r;
+    if (lbm_tile_count(nx, ny, r) + kFin <= simds) return r;
   return half ? 8 : 7;
 }
 
 int lbm_build_tiles(lbm_domain* d) {
   lbm_drop_graphs(d);
   const int nx = d->P.nx, ny = d->P.ny;
-  const int rows = d->rows > 0 ? std::max(kMinTileRows, d->rows) : lbm_auto_rows(nx, ny, d->simds, d->P.storage == LBM_STORE_F16_DEV || d->P.storage == LBM_STORE_BF16_DEV);
+  const bool half = d->P.storage == LBM_STORE_F16_DEV || d->P.storage == LBM_STORE_BF16_DEV;
+  const int rows = d->rows > 0         ? std::max(kMinTileRows, d->rows)
+                   : d->batch_rows > 0 ? d->batch_rows
+                                       : lbm_auto_rows(nx, ny, d->simds, half);
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
   d->tiles_h.clear();
   std::vector<std::pair<int, int>> seg;
