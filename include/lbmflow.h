@@ -184,7 +184,7 @@ int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double* rho_v, dou
  * once; otherwise 7 rows with FP32 storage, 8 with FP16/BF16); values below
  * 2 act as 2.  Results do not depend on it (bitwise).  Synchronises the
  * domain's stream (the pending partial sums move to the new tiling) and
- * drops its replay graphs. */
+ * drops its replay graphs.  LBM_E_STATE while the domain is in a batch. */
 int lbm_set_tile_rows(lbm_domain* d, int rows);
 
 /* Batched execution: n domains (all created on the same device, stepped

@@ -734,6 +734,8 @@ extern "C" int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double*
 extern "C" int lbm_set_tile_rows(lbm_domain* d, int rows) {
   if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
   if (rows < 0) return lbm_fail(LBM_E_INVALID, "rows must be >= 0");
+  // the batch holds copies of the domain's tiles
+  if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch");
   // The pending partial sums of the last launch are stored per tile: keep
   // their totals in tile 0 of the new layout (the finalizers' slices of the
   // new tiling then sum to the same values).

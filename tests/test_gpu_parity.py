@@ -244,7 +244,9 @@ def test_diag_history_records_every_step(L):
 
 def test_batch_equals_solo(L):
     """Uneven domains stepped as one batch give the same fields as each
-    stepped alone (bitwise)."""
+    stepped alone (bitwise); a batched domain cannot be retiled on its own;
+    after the batch the domains (back on their own tile heights, with the
+    pending reductions carried over) keep stepping alone like the solo runs."""
     cfgs = [W.Channel(nx=130, ny=30, heater_len=10, seed=5), W.Channel(nx=250, ny=41, heater_len=16, seed=6),
             W.Channel(nx=64, ny=64, heater_len=20, seed=7)]
     solo = []
@@ -262,6 +264,9 @@ def test_batch_equals_solo(L):
         doms.append(d)
     doms[1].step(0)
     b = L.Batch(doms)
+    with pytest.raises(L.LbmError) as e:
+        doms[0].set_tile_rows(5)
+    assert e.value.code == L.LBM_E_STATE
     b.step(40)  # one 32-step graph, four pairs
     b.sync()
     b.close()
@@ -270,6 +275,18 @@ def test_batch_equals_solo(L):
         assert d.steps == 41
         for k in f:
             assert np.array_equal(f[k], s[k]), k
+    # 25 more steps alone on both sides: fields and diagnostics agree
+    for c, d in zip(cfgs, doms):
+        ref = make_gpu(L, c)
+        ref.init(**c.init_args())
+        ref.step(41)
+        ref.step(25)
+        d.step(25)
+        fr, fd = ref.fields(), d.fields()
+        for k in fr:
+            assert np.array_equal(fr[k], fd[k]), k
+        dr, dd = ref.diag(), d.diag()
+        assert dr["step"] == dd["step"] and dr["mass"] == dd["mass"] and dr["vapor_cells"] == dd["vapor_cells"]
 
 
 def test_channel_1600x200_parity(L):
