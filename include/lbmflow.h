@@ -128,6 +128,7 @@ int lbm_required_bytes(const lbm_params* p, size_t* bytes);
  * Conventions. */
 int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, size_t dev_bytes,
                lbm_domain** out);
+/* LBM_E_STATE (nothing freed) while the domain is in a batch. */
 int lbm_destroy(lbm_domain* d);
 
 /* Wall maps of one side (LBM_SIDE_S bottom, LBM_SIDE_N top), nx entries:
@@ -143,7 +144,8 @@ int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, const doubl
  * post-collision f = f^eq(rho0, 0), g = w_i T0 at every node,
  * with rho0 = the array, or rho_uniform (1 + noise_rel * xi(x, y)) where xi
  * in [-1, 1) is the SplitMix64 variate of seed ^ (y nx + x); T0 = the array
- * or T_uniform.  Resets the step counter and the lagged mean density. */
+ * or T_uniform.  Resets the step counter and the lagged mean density.
+ * LBM_E_STATE while the domain is in a batch. */
 int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_uniform,
                     double T_uniform, double noise_rel, uint64_t seed);
 
@@ -152,11 +154,14 @@ int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double 
  * of 32 and of 2 launches (captured on first use, dropped when the tiling
  * changes).  Results are bitwise the same however nsteps is split. */
 int lbm_step(lbm_domain* d, int64_t nsteps);
+/* Waits for the domain's stream (and its batch's, while it is in one). */
 int lbm_sync(lbm_domain* d);
 int64_t lbm_step_count(const lbm_domain* d);
 
 /* Fields of the current state (post-streaming): rho, actual velocity u_act
- * of Eq. 7, T.  Host FP64 arrays [ny][nx]; any pointer may be NULL. */
+ * of Eq. 7, T.  Host FP64 arrays [ny][nx]; any pointer may be NULL.  The
+ * read-outs, lbm_diag_history and lbm_save of a domain in a batch first
+ * wait for the batch's stream. */
 int lbm_read_fields(lbm_domain* d, double* rho, double* ux, double* uy, double* T);
 /* Same fields into caller device buffers of nx*ny floats (no host copy). */
 int lbm_read_fields_device(lbm_domain* d, float* rho, float* ux, float* uy, float* T);
@@ -169,7 +174,8 @@ int lbm_read_diag(lbm_domain* d, lbm_diag* out);
  * capacity states, oldest first).  *n receives the number written. */
 int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n);
 
-/* Checkpoint: state buffers, outlet memory, lagged means, step counter. */
+/* Checkpoint: state buffers, outlet memory, lagged means, step counter.
+ * lbm_load: LBM_E_STATE while the domain is in a batch. */
 int lbm_save(lbm_domain* d, const char* path);
 int lbm_load(lbm_domain* d, const char* path);
 

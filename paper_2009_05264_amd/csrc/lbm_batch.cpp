@@ -350,6 +350,7 @@ extern "C" int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune
   }
   for (lbm_domain* d : b->doms) {
     d->in_batch = true;
+    d->batch_stream = b->stream;
     d->host.parity = (int)(d->step & 1);
     HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
   }
@@ -399,6 +400,7 @@ extern "C" int lbm_batch_destroy(lbm_batch* b) {
   int rc = LBM_OK;
   for (lbm_domain* d : b->doms) {
     d->in_batch = false;
+    d->batch_stream = nullptr;
     d->host.parity = 0;
     (void)hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice);
     if (d->batch_rows) {

@@ -378,8 +378,16 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   return LBM_OK;
 }
 
+// A batched domain is stepped on its batch's stream: wait for that stream
+// before the domain's own stream reads or writes its state.
+static hipError_t wait_batch(lbm_domain* d) {
+  return d->batch_stream && d->batch_stream != d->stream ? hipStreamSynchronize(d->batch_stream)
+                                                         : hipSuccess;
+}
+
 extern "C" int lbm_destroy(lbm_domain* d) {
   if (!d) return LBM_OK;
+  if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch; destroy the batch first");
   if (d->stream) (void)hipStreamSynchronize(d->stream);
   lbm_drop_graphs(d);
   if (d->own_mem && d->mem) (void)hipFree(d->mem);
@@ -402,6 +410,7 @@ extern "C" int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, 
     tw[x] = (float)T_wall[x];
     d->Tw_h[side][x] = T_wall[x];
   }
+  HIPCHECK(wait_batch(d));  // the new maps apply from the next step on
   HIPCHECK(hipMemcpyAsync(d->psiw_d[side], ps.data(), nx * sizeof(float), hipMemcpyHostToDevice, d->stream));
   HIPCHECK(hipMemcpyAsync(d->Tw_d[side], tw.data(), nx * sizeof(float), hipMemcpyHostToDevice, d->stream));
   if (side == LBM_SIDE_S) {
@@ -418,6 +427,7 @@ extern "C" int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, 
 extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_u,
                                double T_u, double noise, uint64_t seed) {
   if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch");
   const int nx = d->P.nx, ny = d->P.ny;
   const size_t n = (size_t)nx * ny;
   if (!rho0 && !(rho_u > 0)) return lbm_fail(LBM_E_INVALID, "rho_uniform must be positive");
@@ -487,6 +497,7 @@ extern "C" int lbm_step(lbm_domain* d, int64_t nsteps) {
 
 extern "C" int lbm_sync(lbm_domain* d) {
   if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
+  HIPCHECK(wait_batch(d));
   HIPCHECK(hipStreamSynchronize(d->stream));
   return LBM_OK;
 }
@@ -495,6 +506,7 @@ extern "C" int64_t lbm_step_count(const lbm_domain* d) { return d ? d->step : -1
 
 static int readout(lbm_domain* d) {
   if (!d->inited) return lbm_fail(LBM_E_STATE, "lbm_init_fields has not been called");
+  HIPCHECK(wait_batch(d));
   // the kernel adds the descriptor's parity: pass the phase that lands on step & 1
   HIPCHECK(lbm_launch_readout(d->P.storage, d->tiles_d, d->ntiles,
                               (int)(d->step & 1) ^ d->host.parity, d->stream));
@@ -554,6 +566,7 @@ extern "C" int lbm_read_diag(lbm_domain* d, lbm_diag* out) {
 extern "C" int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n) {
   if (!d || !out || !n) return lbm_fail(LBM_E_INVALID, "NULL argument");
   std::vector<DiagRec> ring(kRing);
+  HIPCHECK(wait_batch(d));
   HIPCHECK(hipStreamSynchronize(d->stream));
   HIPCHECK(hipMemcpy(ring.data(), d->host.ring, kRing * sizeof(DiagRec), hipMemcpyDeviceToHost));
   std::vector<DiagRec> valid;
@@ -597,6 +610,7 @@ extern "C" int lbm_save(lbm_domain* d, const char* path) {
   std::vector<char> st(L.state_bytes), fo(L.fold_bytes), pa(pb);
   double rb[2 * kFin * kPartials];
   long long sd;
+  HIPCHECK(wait_batch(d));
   HIPCHECK(hipStreamSynchronize(d->stream));
   HIPCHECK(hipMemcpy(st.data(), d->host.buf[ph], L.state_bytes, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(fo.data(), d->host.fold[ph], L.fold_bytes, hipMemcpyDeviceToHost));
@@ -626,6 +640,7 @@ extern "C" int lbm_save(lbm_domain* d, const char* path) {
 
 extern "C" int lbm_load(lbm_domain* d, const char* path) {
   if (!d || !path) return lbm_fail(LBM_E_INVALID, "NULL argument");
+  if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch");
   FILE* f = fopen(path, "rb");
   if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s", path);
   CkptHeader h{};

@@ -41,6 +41,7 @@ struct lbm_domain {
   int64_t step = 0;
   bool inited = false;
   bool in_batch = false;
+  hipStream_t batch_stream = nullptr;  // stream the domain's batch runs on (while in one)
   std::vector<GraphEntry> graphs;  // replay graphs of this domain: [0] two steps, [1] 32 steps
 };
 

@@ -264,10 +264,15 @@ def test_batch_equals_solo(L):
         doms.append(d)
     doms[1].step(0)
     b = L.Batch(doms)
-    with pytest.raises(L.LbmError) as e:
-        doms[0].set_tile_rows(5)
-    assert e.value.code == L.LBM_E_STATE
+    for call in (lambda: doms[0].set_tile_rows(5), lambda: doms[1].init(**cfgs[1].init_args())):
+        with pytest.raises(L.LbmError) as e:
+            call()
+        assert e.value.code == L.LBM_E_STATE
     b.step(40)  # one 32-step graph, four pairs
+    # a read-out of a domain stepped on another stream waits for the batch
+    early = doms[2].fields()
+    for k in early:
+        assert np.array_equal(early[k], solo[2][k]), k
     b.sync()
     b.close()
     for s, d in zip(solo, doms):
