@@ -193,6 +193,16 @@ int lbm_maxwell(const lbm_params* p, double T, double* rho_l, double* rho_v, dou
  * drops its replay graphs.  LBM_E_STATE while the domain is in a batch. */
 int lbm_set_tile_rows(lbm_domain* d, int rows);
 
+/* Host only (no device call): the tiles lbm_create makes for an nx x ny
+ * domain with the given storage on a device of `simds` SIMDs (0: 1024, the
+ * MI355X count), at `rows` rows per tile (0: the automatic choice).  Tile t
+ * covers columns [x0[t], min(x0[t] + 60, nx)) and rows [y0[t], y1[t]), in
+ * launch order; the first min(max, count) tiles are written (the arrays may
+ * be NULL when max is 0), *n receives the count and *rows_used (may be NULL)
+ * the rows per tile.  LBM_E_INVALID for nx or ny below 3 or bad pointers. */
+int lbm_tile_plan(int nx, int ny, int storage, int simds, int rows, int* rows_used, int* x0, int* y0,
+                  int* y1, int max, int* n);
+
 /* Batched execution: n domains (all created on the same device, stepped
  * together, one launch per step over the concatenated tile table, replayed
  * from captured hipGraphs as in lbm_step).  tune_cache_json: NULL = no autotuning:

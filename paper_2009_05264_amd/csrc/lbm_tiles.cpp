@@ -76,23 +76,18 @@ static int lbm_auto_rows(int nx, int ny, int simds, bool half) {
   return half ? 8 : 7;
 }
 
-int lbm_build_tiles(lbm_domain* d) {
-  lbm_drop_graphs(d);
-  const int nx = d->P.nx, ny = d->P.ny;
-  const bool half = d->P.storage == LBM_STORE_F16_DEV || d->P.storage == LBM_STORE_BF16_DEV;
-  const int rows = d->rows > 0         ? std::max(kMinTileRows, d->rows)
-                   : d->batch_rows > 0 ? d->batch_rows
-                                       : lbm_auto_rows(nx, ny, d->simds, half);
+// The tile list of an nx x ny domain at `rows` rows per tile, in launch
+// order (local indices and the descriptor pointer left to the caller).
+static void plan_tiles(int nx, int ny, int rows, bool isothermal, std::vector<Tile>& out) {
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
-  d->tiles_h.clear();
+  out.clear();
   std::vector<std::pair<int, int>> seg;
   for (int t = 0; t < strips; ++t) {
     const int x0 = t * kStripInterior;
     const bool column_edge = strip_is_column_edge(x0, nx);
     strip_segments(ny, rows, column_edge, seg);
     for (const auto& sg : seg) {
-      Tile tl;
-      tl.d = d->dev;
+      Tile tl{};
       tl.x0 = x0;
       tl.y0 = sg.first;
       tl.y1 = sg.second;
@@ -103,17 +98,50 @@ int lbm_build_tiles(lbm_domain* d) {
                : (tl.y0 - 2 >= 1 && r_end <= ny - 2) ? kTileInterior
                                                       : kTileRowEdge;
       };
-      tl.kind = kind(tl.y1 + 1) | kind(tl.y1) << 2 | (d->P.isothermal ? kTileIsothermal : 0);
-      tl.pad = 0;
-      d->tiles_h.push_back(tl);
+      tl.kind = kind(tl.y1 + 1) | kind(tl.y1) << 2 | (isothermal ? kTileIsothermal : 0);
+      out.push_back(tl);
     }
   }
   // Row-major launch order: the tiles in flight at any time cover a few
   // full-width row bands, so every plane is streamed in long contiguous
   // runs (DRAM pages, TLB reach) rather than in narrow vertical bands.
-  std::stable_sort(d->tiles_h.begin(), d->tiles_h.end(), [](const Tile& a, const Tile& b) {
+  std::stable_sort(out.begin(), out.end(), [](const Tile& a, const Tile& b) {
     return a.y0 != b.y0 ? a.y0 < b.y0 : a.x0 < b.x0;
   });
+}
+
+static bool half_storage(int storage) {
+  return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV;
+}
+
+extern "C" int lbm_tile_plan(int nx, int ny, int storage, int simds, int rows, int* rows_used, int* x0,
+                             int* y0, int* y1, int max, int* n) {
+  if (nx < 3 || ny < 3 || rows < 0 || max < 0 || !n || (max > 0 && (!x0 || !y0 || !y1)))
+    return lbm_fail(LBM_E_INVALID, "bad tile-plan arguments");
+  if (storage < LBM_STORE_F32 || storage > LBM_STORE_BF16_DEV)
+    return lbm_fail(LBM_E_INVALID, "unknown storage %d", storage);
+  const int r = rows > 0 ? std::max(kMinTileRows, rows)
+                         : lbm_auto_rows(nx, ny, simds > 0 ? simds : 1024, half_storage(storage));
+  std::vector<Tile> tiles;
+  plan_tiles(nx, ny, r, false, tiles);
+  for (int i = 0; i < max && i < (int)tiles.size(); ++i) {
+    x0[i] = tiles[i].x0;
+    y0[i] = tiles[i].y0;
+    y1[i] = tiles[i].y1;
+  }
+  if (rows_used) *rows_used = r;
+  *n = (int)tiles.size();
+  return LBM_OK;
+}
+
+int lbm_build_tiles(lbm_domain* d) {
+  lbm_drop_graphs(d);
+  const int nx = d->P.nx, ny = d->P.ny;
+  const int rows = d->rows > 0         ? std::max(kMinTileRows, d->rows)
+                   : d->batch_rows > 0 ? d->batch_rows
+                                       : lbm_auto_rows(nx, ny, d->simds, half_storage(d->P.storage));
+  plan_tiles(nx, ny, rows, d->P.isothermal != 0, d->tiles_h);
+  for (Tile& tl : d->tiles_h) tl.d = d->dev;
   for (size_t i = 0; i < d->tiles_h.size(); ++i) d->tiles_h[i].local = (int)i;
   if ((int)d->tiles_h.size() > d->host.pstride)
     return lbm_fail(LBM_E_CAP, "tile table of %zu tiles exceeds its capacity %d", d->tiles_h.size(),

@@ -95,6 +95,9 @@ def lib():
             "lbm_load": (C.c_int, [vp, C.c_char_p]),
             "lbm_maxwell": (C.c_int, [C.POINTER(Params), C.c_double, dp, dp, dp]),
             "lbm_set_tile_rows": (C.c_int, [vp, C.c_int]),
+            "lbm_tile_plan": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                        C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int,
+                                        C.POINTER(C.c_int)]),
             "lbm_batch_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_char_p, C.POINTER(vp)]),
             "lbm_batch_step": (C.c_int, [vp, C.c_int64]),
             "lbm_batch_sync": (C.c_int, [vp]),
@@ -151,6 +154,15 @@ def maxwell(p: Params, T: float):
     rl, rv, ps = C.c_double(), C.c_double(), C.c_double()
     _check(lib().lbm_maxwell(C.byref(p), float(T), C.byref(rl), C.byref(rv), C.byref(ps)))
     return rl.value, rv.value, ps.value
+
+
+def tile_plan(nx: int, ny: int, storage: int = 1, simds: int = 0, rows: int = 0):
+    """The tiling lbm_create makes (host only): (rows per tile, [(x0, y0, y1), ...])."""
+    n, r = C.c_int(), C.c_int()
+    _check(lib().lbm_tile_plan(nx, ny, storage, simds, rows, C.byref(r), None, None, None, 0, C.byref(n)))
+    a = [(C.c_int * max(n.value, 1))() for _ in range(3)]
+    _check(lib().lbm_tile_plan(nx, ny, storage, simds, rows, C.byref(r), a[0], a[1], a[2], n.value, C.byref(n)))
+    return r.value, [(a[0][i], a[1][i], a[2][i]) for i in range(n.value)]
 
 
 def stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int | None = None):
