@@ -59,6 +59,7 @@ typedef struct {
   double T_iso;              /* frozen temperature when isothermal           */
   double rho_mid;            /* vapour threshold for the diagnostics         */
   double rho_out;            /* outlet density of the constant-pressure outlet */
+  double G_wet;              /* adhesion strength G_wet of Eq. 15            */
   int32_t nx, ny;
   int32_t bc_x, bc_y;
   int32_t isothermal;        /* 1: temperature frozen at T_iso, g not evolved */
@@ -77,7 +78,7 @@ typedef struct {
   int64_t step;      /* number of completed steps               */
   double *fs, *gs;   /* post-collision distributions [9][ny][nx] */
   double *fold;      /* convective-outlet memory [3][ny], i = 3,6,7 */
-  double rbar[2];    /* mean density of the two previous states  */
+  double rbar;       /* mean density of the previous state (Eq. 14) */
   double *Tw_s, *Tw_n, *rw_s, *rw_n, *psiw_s, *psiw_n;
   int *heater;       /* bottom-wall heater flags [nx]            */
   /* work arrays of the state being processed */
@@ -366,13 +367,15 @@ static void macro_and_forces(oc_state* S) {
   S->diag[D_P_OUT] = NODE(S->p, nx - 1, ny / 2);
 
   /* S3 forces.  Eq. 9 with psi(x1) inside the sums and G1 = 2g,
-   * G2 = g/2 (Eq. 10).  Adhesion (Eq. 15): a solid neighbour enters the
-   * same two sums with the pseudopotential of the false wall density,
-   * psi_w = psi(rho_w, T_wall), so that rho_w equal to the local density
-   * exerts no net force.  Buoyancy Eq. 14 in the (rho - rho_avg) g_a form
-   * with rho_avg the mean density of the state two steps back. */
+   * G2 = g/2 (Eq. 10), over the fluid neighbours.  Solid neighbours enter
+   * the adhesion force of Eq. 15 instead: -G_wet psi(x) sum_i w_i psi_w c_i,
+   * with psi_w = psi(rho_w, T_wall) of the false wall density of that solid
+   * cell.  Buoyancy Eq. 14 as a force density, rho g_a (1 - rho_avg/rho) =
+   * (rho - rho_avg) g_a, with rho_avg the mean density of the whole domain
+   * taken at the previous time level (the explicit time level of every other
+   * neighbour quantity of the step). */
   const double G1 = 2.0 * P->g, G2 = 0.5 * P->g;
-  const double rbar = S->rbar[1];
+  const double rbar = S->rbar;
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y) {
     for (int x = 0; x < nx; ++x) {
@@ -384,8 +387,8 @@ static void macro_and_forces(oc_state* S) {
         if (is_solid_row(P, y1)) {
           const int xm = wall_x(P, x1);
           const double pw = y1 < 0 ? S->psiw_s[xm] : S->psiw_n[xm];
-          fw_x += -P->beta * psi0 * Gi * pw * CX[i] - 0.5 * (1.0 - P->beta) * Gi * pw * pw * CX[i];
-          fw_y += -P->beta * psi0 * Gi * pw * CY[i] - 0.5 * (1.0 - P->beta) * Gi * pw * pw * CY[i];
+          fw_x += -P->G_wet * psi0 * W[i] * pw * CX[i];
+          fw_y += -P->G_wet * psi0 * W[i] * pw * CY[i];
         } else {
           if (P->bc_y == BCY_PERIODIC) y1 = wrap(y1, ny);
           x1 = P->bc_x == BCX_PERIODIC ? wrap(x1, nx) : clampi(x1, 0, nx - 1);
@@ -550,7 +553,8 @@ void oc_init(void* h, const double* rho0, const double* T0, double rho_u, double
   const int ko[3] = {3, 6, 7};
   for (int k = 0; k < 3; ++k)
     for (int y = 0; y < ny; ++y) S->fold[k * ny + y] = AT(S->fs, ko[k], nx - 1, y);
-  S->rbar[0] = S->rbar[1] = sum / (double)S->N;
+  /* the buoyancy of the first state uses the mean initial density */
+  S->rbar = sum / (double)S->N;
   S->step = 0;
 }
 
@@ -582,8 +586,7 @@ void oc_step(void* h, int64_t n) {
       }
     }
     if (P->bc_x == BCX_CHANNEL) memcpy(S->fold, S->fold_new, 3 * (size_t)ny * sizeof(double));
-    S->rbar[1] = S->rbar[0];
-    S->rbar[0] = S->diag[D_MASS] / (double)S->N;
+    S->rbar = S->diag[D_MASS] / (double)S->N;
     S->step++;
   }
 }
@@ -633,11 +636,10 @@ void oc_get_streamed(void* h, double* f, double* g) {
   memcpy(f, S->f, 9 * (size_t)S->N * sizeof(double));
   memcpy(g, S->g, 9 * (size_t)S->N * sizeof(double));
 }
-void oc_get_rbar(void* h, double* out2) {
-  oc_state* S = (oc_state*)h;
-  out2[0] = S->rbar[0];
-  out2[1] = S->rbar[1];
-}
+/* Mean density the next evaluation of the force uses (Eq. 14); settable so
+ * that a test can give a state a known lagged mean. */
+double oc_get_rbar(void* h) { return ((oc_state*)h)->rbar; }
+void oc_set_rbar(void* h, double v) { ((oc_state*)h)->rbar = v; }
 
 /* ---- single-node entry points for the pin tests ------------------------ */
 int oc_eos(const oc_params* P, double rho, double T, double* out3) {

@@ -65,7 +65,9 @@ def lib():
         L.oc_get_state.argtypes = [C.c_void_p, dp, dp]
         L.oc_set_state.argtypes = [C.c_void_p, dp, dp]
         L.oc_get_streamed.argtypes = [C.c_void_p, dp, dp]
-        L.oc_get_rbar.argtypes = [C.c_void_p, dp]
+        L.oc_get_rbar.restype = C.c_double
+        L.oc_get_rbar.argtypes = [C.c_void_p]
+        L.oc_set_rbar.argtypes = [C.c_void_p, C.c_double]
         L.oc_eos.restype = C.c_int
         L.oc_eos.argtypes = [C.c_void_p, C.c_double, C.c_double, dp]
         L.oc_Tc.restype = C.c_double
@@ -82,7 +84,7 @@ class _CParams(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "a", "b", "R", "omega", "beta", "c0", "g", "s_nu", "s_e", "s_eps", "s_q",
         "tau_g", "c_v", "ga_x", "ga_y", "fb_x", "fb_y", "u_in", "T_in", "U_out",
-        "T_iso", "rho_mid", "rho_out")] + [(n, C.c_int32) for n in (
+        "T_iso", "rho_mid", "rho_out", "G_wet")] + [(n, C.c_int32) for n in (
         "nx", "ny", "bc_x", "bc_y", "isothermal", "single_phase")]
 
 
@@ -125,6 +127,7 @@ class Params:
     T_iso: float = 0.0
     rho_mid: float = 0.0
     rho_out: float = 0.0     # outlet density of BCX_CHANNEL_P
+    G_wet: float | None = None  # adhesion strength of Eq. 15 (None: neutral_G_wet)
     bc_x: int = BCX_CHANNEL
     bc_y: int = BCY_WALLS
     isothermal: int = 0
@@ -152,6 +155,8 @@ class Params:
                 c.s_q = s_q
             elif n == "U_out":
                 c.U_out = self.u_in if self.U_out is None else self.U_out
+            elif n == "G_wet":
+                c.G_wet = self.neutral_G_wet if self.G_wet is None else self.G_wet
             else:
                 setattr(c, n, getattr(self, n))
         return c
@@ -159,6 +164,16 @@ class Params:
     @property
     def Tc(self) -> float:
         return crit_temperature(self.a, self.b, self.R)
+
+    @property
+    def neutral_G_wet(self) -> float:
+        """The G_wet of Eq. 15 (not printed in the paper) at which a wall whose
+        false density equals the adjacent fluid density exerts no net force.
+        Eq. 10 with g1 = 2g, g2 = g/2 is G_i = 18 g w_i on D2Q9, and a flat
+        wall removes the solid neighbours from both sums of Eq. 9, whose
+        missing pull is (1 + beta)/2 sum_solid G_i psi^2 c_i; Eq. 15 returns
+        it when G_wet w_i = (1 + beta)/2 G_i, i.e. G_wet = 9 g (1 + beta)."""
+        return 9.0 * self.g * (1.0 + self.beta)
 
 
 def _dp(a):
@@ -250,10 +265,13 @@ class Oracle:
         lib().oc_get_streamed(self.h, _dp(f), _dp(g))
         return f, g
 
-    def rbar(self):
-        out = np.zeros(2)
-        lib().oc_get_rbar(self.h, _dp(out))
-        return out
+    def rbar(self) -> float:
+        """Mean density the force of the next evaluation uses (Eq. 14): that
+        of the previous state."""
+        return float(lib().oc_get_rbar(self.h))
+
+    def set_rbar(self, v: float):
+        lib().oc_set_rbar(self.h, float(v))
 
 
 def collide_f_node(P: Params, f, Fx, Fy):

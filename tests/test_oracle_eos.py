@@ -61,6 +61,24 @@ def test_psi_defined_in_working_range(oracle_mod):
     assert O.eos(P, 9.5, 1.2 * P.Tc)[3]
 
 
+def test_psi_identity_and_pressure(oracle_mod):
+    """Eq. 11 inverted: c0 g psi^2 / 2 + c_s^2 rho = p for every state the
+    oracle evaluates, and p itself equals the Peng-Robinson pressure of
+    Eq. 12 written in molar volume by the separate numpy code of the Maxwell
+    construction (pr_pressure_v), so a slip in either the EOS or the psi map
+    (a constant, a sign, c0 against g) fails here."""
+    O = oracle_mod
+    for omega in (0.32, 0.344):
+        P = O.Params(omega=omega)
+        for tr in (0.6, 0.86, 0.9, 1.0, 1.2):
+            T = tr * P.Tc
+            for rho in (0.05, 0.38, 1.0, 2.657, 5.0, 6.5, 8.0):
+                p, psi, _, clamped = O.eos(P, rho, T)
+                assert not clamped
+                assert P.c0 * P.g * psi ** 2 / 2 + rho / 3 == pytest.approx(p, rel=1e-13, abs=1e-16)
+                assert p == pytest.approx(O.pr_pressure_v(1.0 / rho, T, omega=omega), rel=1e-12, abs=1e-16)
+
+
 def _check_maxwell(O, T, omega):
     rl, rv, ps = O.maxwell(T, omega=omega)
     P = O.Params(omega=omega)

@@ -25,26 +25,61 @@ def test_uniform_state_has_no_force(oracle_mod):
 
 
 def test_wall_force_closed_form(oracle_mod):
-    """Uniform fluid next to a wall of false density rho_w: on the first row
-    F_y = 3[beta psi (psi - psi_w) + (1-beta)/2 (psi^2 - psi_w^2)] (the solid
-    cells of the row below carry psi_w in Eq. 9's sums, G1 + 2 G2 = -3), and
-    zero when rho_w equals the fluid density."""
+    """Uniform fluid (pseudopotential psi) over a flat bottom wall of false
+    density rho_w (psi_w).  On the first row the solid cells are the sources
+    of directions 4, 7, 8, so Eq. 9 sums only 1, 2, 3, 5, 6:
+    sum_fluid G_i c_iy = g1 + 2 g2 = 3g (Eq. 10, g1 = 2g, g2 = g/2), and
+    F_SC,y = -(beta + (1 - beta)/2) psi^2 3g.  Eq. 15 adds
+    -G_wet psi psi_w (w_4 c_4y + w_7 c_7y + w_8 c_8y) = G_wet psi psi_w / 6.
+    Written out by hand from the equations, for the default G_wet and for
+    two others; the rows above feel no force."""
     O = oracle_mod
     Ts = _ts(O)
     rho = 6.2
-    for rw in (rho, 3.0, 0.4):
-        P = O.Params(nx=6, ny=8, bc_x=O.BCX_PERIODIC, bc_y=O.BCY_WALLS, isothermal=1, T_iso=Ts, ga_y=0.0)
+    for gw in (None, -5.0, -30.0):
+        for rw in (rho, 3.0, 0.4):
+            P = O.Params(nx=6, ny=8, bc_x=O.BCX_PERIODIC, bc_y=O.BCY_WALLS, isothermal=1, T_iso=Ts,
+                         ga_y=0.0, G_wet=gw)
+            o = O.Oracle(P)
+            o.set_wall(0, Ts, rw)
+            o.set_wall(1, Ts, rho)
+            o.init(rho_u=rho, T_u=Ts)
+            F = o.fields(extra=True)
+            psi = O.eos(P, rho, Ts)[1]
+            pw = O.eos(P, rw, Ts)[1]
+            G = P.neutral_G_wet if gw is None else gw
+            expect = -0.5 * (1.0 + P.beta) * 3.0 * P.g * psi ** 2 + G * psi * pw / 6.0
+            assert np.allclose(F["Fy"][0], expect, rtol=1e-12, atol=1e-15)
+            assert np.abs(F["Fx"]).max() < 1e-14
+            if gw is None:
+                # the top wall at the fluid density is neutral (mirror of row 0)
+                assert np.abs(F["Fy"][1:]).max() < 1e-13
+            else:
+                assert np.abs(F["Fy"][1:-1]).max() < 1e-13
+
+
+def test_adhesion_default_is_neutral_and_attracts_above_it(oracle_mod):
+    """With the default G_wet = 9 g (1 + beta) a wall at the fluid's own
+    density exerts no force (the flat-wall sum above becomes
+    (3/2) g (1 + beta) psi (psi_w - psi)), a denser wall pulls the fluid
+    towards it (F_y < 0 over a bottom wall) and a lighter one pushes it away;
+    the force is linear in psi_w (Eq. 15)."""
+    O = oracle_mod
+    Ts = _ts(O)
+    rho = 5.0
+    P = O.Params(nx=5, ny=6, bc_x=O.BCX_PERIODIC, bc_y=O.BCY_WALLS, isothermal=1, T_iso=Ts, ga_y=0.0)
+    assert P.neutral_G_wet == pytest.approx(-19.44, rel=1e-12)
+    fy = {}
+    for rw in (2.0, rho, 6.4):
         o = O.Oracle(P)
         o.set_wall(0, Ts, rw)
         o.set_wall(1, Ts, rho)
         o.init(rho_u=rho, T_u=Ts)
-        F = o.fields(extra=True)
-        psi = O.eos(P, rho, Ts)[1]
-        pw = O.eos(P, rw, Ts)[1]
-        expect = 3.0 * (P.beta * psi * (psi - pw) + 0.5 * (1 - P.beta) * (psi ** 2 - pw ** 2))
-        assert np.allclose(F["Fy"][0], expect, rtol=1e-12, atol=1e-15)
-        assert np.abs(F["Fx"]).max() < 1e-14
-        assert np.abs(F["Fy"][1:]).max() < 1e-13  # top wall at rho: neutral
+        fy[rw] = o.fields(extra=True)["Fy"][0, 0]
+        psi, pw = O.eos(P, rho, Ts)[1], O.eos(P, rw, Ts)[1]
+        assert fy[rw] == pytest.approx(1.5 * P.g * (1 + P.beta) * psi * (pw - psi), rel=1e-12, abs=1e-15)
+    assert abs(fy[rho]) < 1e-14
+    assert fy[6.4] < 0 < fy[2.0]
 
 
 def test_force_converges_to_continuum_form(oracle_mod):

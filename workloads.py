@@ -7,15 +7,21 @@ the method's arithmetic.  The numeric constants are inputs:
   * RHO_L, RHO_V: Maxwell coexistence densities at 0.86 Tc, omega = 0.344
     (pinned against the oracle's Maxwell construction);
   * RHO_W_60: false wall density giving a ~60 degree contact angle at
-    0.86 Tc (from the oracle's sessile-drop sweep, tests/golden/contact_angle_0p86Tc.json).
+    0.86 Tc (from the oracle's sessile-drop sweep, tests/golden/contact_angle_0p86Tc.json);
+    wall_density_for_angle() reads that stored table backwards for any angle
+    of its partial-wetting range.
 The workloads follow the flow-boiling channel of Sec. 2C of the paper with
 the sizes of the benchmark configurations (no dataset is involved).
 """
 from __future__ import annotations
 
+import json
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
+
+CA_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "contact_angle_0p86Tc.json")
 
 TC = 0.07292200407413424
 TSAT_FRAC = 0.86
@@ -36,6 +42,7 @@ class Channel:
     rho_w: float = RHO_W_60
     seed: int = 1
     noise: float = 1e-3
+    theta: float | None = None  # contact angle the wall density was chosen for (degrees)
     steps: int = 2000
     extra: dict = field(default_factory=dict)
 
@@ -75,6 +82,19 @@ class Channel:
         return dict(rho_u=RHO_L, T_u=self.T_sat, noise=self.noise, seed=self.seed)
 
 
+def wall_density_for_angle(theta_deg: float) -> float:
+    """False wall density whose sessile-drop contact angle at 0.86 Tc is
+    theta_deg: piecewise-linear inverse of the stored calibration table over
+    its partial-wetting rows (0 < theta < 180)."""
+    tab = json.load(open(CA_TABLE))["table"]
+    rows = [(t["theta_deg"], t["rho_w"]) for t in tab if t["theta_deg"] is not None and 0 < t["theta_deg"] < 180]
+    th = np.array([r[0] for r in rows])[::-1]  # increasing angle
+    rw = np.array([r[1] for r in rows])[::-1]
+    if not th[0] <= theta_deg <= th[-1]:
+        raise ValueError(f"contact angle {theta_deg} outside the calibrated range [{th[0]:.1f}, {th[-1]:.1f}]")
+    return float(np.interp(theta_deg, th, rw))
+
+
 def c1() -> Channel:
     """200x50 channel, 20-cell heater at 0.1 T_sat superheat, u_in = 0.005."""
     return Channel()
@@ -90,17 +110,32 @@ C2_SWEEP = [(s, u) for s in (0.05, 0.10, 0.15) for u in (0.002, 0.005, 0.01)]
 
 def ensemble(n: int = 64, seed: int = 4, steps: int = 20000) -> list[Channel]:
     """Uneven channels: Lx in {400, 800, 1200, 1600}, Ly in {50, 100, 200},
-    u_in ~ U[0.002, 0.01], superheat ~ U[0.05, 0.2], wettability drawn around
-    the calibrated value; heater 0.4 Ly cells, centred."""
+    u_in ~ U[0.002, 0.01], superheat ~ U[0.05, 0.2], contact angle
+    ~ U[30, 120] degrees turned into a wall density through the calibration
+    table; heater 0.4 Ly cells, centred."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
         nx = int(rng.choice([400, 800, 1200, 1600]))
         ny = int(rng.choice([50, 100, 200]))
-        out.append(Channel(nx=nx, ny=ny, u_in=float(rng.uniform(0.002, 0.01)),
-                           superheat=float(rng.uniform(0.05, 0.2)), heater_len=int(0.4 * ny),
-                           rho_w=float(rng.uniform(3.0, 4.6)), seed=1000 + i, steps=steps))
+        c = Channel(nx=nx, ny=ny, u_in=float(rng.uniform(0.002, 0.01)),
+                    superheat=float(rng.uniform(0.05, 0.2)), heater_len=int(0.4 * ny), seed=1000 + i,
+                    steps=steps)
+        c.theta = float(rng.uniform(30.0, 120.0))
+        # below the smallest partial-wetting angle of the table (31.7
+        # degrees; a film forms beyond it) the wall density of that angle
+        c.rho_w = wall_density_for_angle(max(c.theta, MIN_PARTIAL_ANGLE))
+        out.append(c)
     return out
+
+
+def _partial_wetting_range():
+    tab = json.load(open(CA_TABLE))["table"]
+    th = [t["theta_deg"] for t in tab if t["theta_deg"] is not None and 0 < t["theta_deg"] < 180]
+    return min(th), max(th)
+
+
+MIN_PARTIAL_ANGLE, MAX_PARTIAL_ANGLE = _partial_wetting_range()
 
 
 def roofline_channel() -> Channel:
