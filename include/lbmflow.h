@@ -11,8 +11,10 @@
  *     temperature gradient;
  *   - moments (Eqs. 4, 6, 17), the Peng-Robinson EOS (Eq. 12) and the
  *     pseudopotential (Eq. 11);
- *   - the beta-weighted Shan-Chen force (Eqs. 8-10), adhesion through the
- *     false wall density (Eq. 15), buoyancy (Eq. 14);
+ *   - the beta-weighted Shan-Chen force (Eqs. 8-10) over the fluid
+ *     neighbours, adhesion -G_wet psi(x) sum_solid w_i psi(rho_w) c_i through
+ *     the false wall density (Eq. 15), buoyancy (rho - rho_avg) g_a (Eq. 14)
+ *     with rho_avg the mean density of the previous state;
  *   - exact-difference forcing (Eqs. 5, 7) in a multiple-relaxation-time
  *     collision that reduces to the BGK operator of Eq. 2 when all rates are
  *     equal;
@@ -92,6 +94,9 @@ typedef struct {
   double rho_mid;                /* vapour threshold for diagnostics       */
   double rho_ref, T_ref;         /* reference state of *_DEV storage       */
   double rho_out;                /* outlet density of LBM_BCX_CHANNEL_P (> 0) */
+  double G_wet;                  /* adhesion strength of Eq. 15: a solid neighbour  */
+                                 /* at c_i adds -G_wet psi(x) w_i psi(rho_w) c_i;   */
+                                 /* default lbm_neutral_G_wet (finite)              */
 } lbm_params;
 
 typedef struct lbm_domain lbm_domain;
@@ -115,6 +120,12 @@ const char* lbm_last_error(void);
 
 /* Fill p with the defaults (200x50 channel, PR constants of Sec. 2A). */
 int lbm_params_default(lbm_params* p);
+/* The G_wet of Eq. 15 (not printed in the paper) at which a flat wall whose
+ * false density equals the adjacent fluid's exerts no net force on it:
+ * 9 g (1 + beta), since Eq. 10 on D2Q9 is G_i = 18 g w_i and Eq. 9 over the
+ * fluid neighbours alone lacks (1 + beta)/2 sum_solid G_i psi^2 c_i.
+ * Host only; 0 for NULL. */
+double lbm_neutral_G_wet(const lbm_params* p);
 
 /* Device bytes a domain with these parameters needs (state buffers, outlet
  * memory, wall maps, reductions and read-out fields). */
@@ -150,9 +161,15 @@ int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double 
                     double T_uniform, double noise_rel, uint64_t seed);
 
 /* Enqueue nsteps time steps (the update of Sec. 2 summarised at the top of
- * this file) on the domain's stream (nsteps >= 0): one kernel launch per step; from 8 steps on, replayed from captured hipGraphs
- * of 32 and of 2 launches (captured on first use, dropped when the tiling
- * changes).  Results are bitwise the same however nsteps is split. */
+ * this file) on the domain's stream (nsteps >= 0): one kernel launch per
+ * step.  From 2 steps on they are replayed from captured hipGraphs of 2, 4,
+ * 8, 16 and 32 launches (all five captured by the first call of 2 or more
+ * steps, before any is launched; dropped when the tiling changes): repeats
+ * of the 32-launch graph, then at most one of each shorter one, plus a
+ * single launch for an odd step.  nsteps == 0 enqueues nothing and captures
+ * the five graphs if they are not captured yet (so that a timed call
+ * captures nothing).  Results are bitwise the same however nsteps is
+ * split. */
 int lbm_step(lbm_domain* d, int64_t nsteps);
 /* Waits for the domain's stream (and its batch's, while it is in one). */
 int lbm_sync(lbm_domain* d);
@@ -174,7 +191,11 @@ int lbm_read_diag(lbm_domain* d, lbm_diag* out);
  * capacity states, oldest first).  *n receives the number written. */
 int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n);
 
-/* Checkpoint: state buffers, outlet memory, lagged means, step counter.
+/* Checkpoint: state buffer, outlet memory, the mean density the next step
+ * uses, pending diagnostics, step counter.  Independent of the tiling: a
+ * checkpoint loads into a domain of the same geometry and storage whatever
+ * its tile rows.  The per-step records of lbm_diag_history are not saved:
+ * after lbm_load they restart with the states the loaded run produces.
  * lbm_load: LBM_E_STATE while the domain is in a batch. */
 int lbm_save(lbm_domain* d, const char* path);
 int lbm_load(lbm_domain* d, const char* path);
@@ -208,11 +229,15 @@ int lbm_tile_plan(int nx, int ny, int storage, int simds, int rows, int* rows_us
  * from captured hipGraphs as in lbm_step).  tune_cache_json: NULL = no autotuning:
  * domains on automatic rows (lbm_set_tile_rows 0) get one tile height chosen
  * for the batch's combined tiles (fewest rounds of waves on the SIMDs times
- * the row steps of a tile), and their own choice back when the batch is
- * destroyed; "" = autotune on the batch without a cache file,
- * otherwise a text file the autotuner reads and appends to.  Results do not
- * depend on the choice (bitwise). */
+ * the row steps of a tile); "" = autotune on the batch without a cache file,
+ * otherwise a text file the autotuner reads and appends to.  The autotuner
+ * times each option by stepping the batch: those are real steps of every
+ * domain (22 per option, 15 options: rows 4, 6, 7, 8, 12 x grids of one
+ * workgroup per tile, 8 or 16 per compute unit), counted by lbm_step_count.
+ * lbm_batch_destroy gives every domain its own rows setting back.  Results
+ * do not depend on the tile choice (bitwise). */
 int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune_cache_json, lbm_batch** out);
+/* As lbm_step, over all domains of the batch (nsteps == 0: capture only). */
 int lbm_batch_step(lbm_batch* b, int64_t nsteps);
 int lbm_batch_sync(lbm_batch* b);
 /* Synchronises the batch's stream and hands its domains back for stepping
@@ -261,6 +286,7 @@ typedef struct {
   size_t resident_bytes, peak_resident_bytes;
   double lups;          /* lattice updates completed by the server        */
   double busy_seconds;  /* host time spent inside device quanta           */
+  int64_t failed;       /* requests in LBM_REQ_FAILED                     */
 } lbm_server_info;
 
 /* hbm_cap_bytes > 0: bound on the summed footprint of resident requests;
@@ -275,7 +301,11 @@ int lbm_server_submit(lbm_server* s, const lbm_params* p, const lbm_request* r, 
  * receives the number of requests still running. */
 int lbm_server_pump(lbm_server* s, int* running);
 /* *state = LBM_REQ_*; *time_to_solution_s (may be NULL) = completion minus
- * arrival in seconds once done, else -1. */
+ * arrival in seconds once done, else -1.  LBM_REQ_FAILED: the request could
+ * not be started (its lbm_create/lbm_init_fields error), or its density or
+ * temperature turned non-finite (LBM_E_NAN; checked on every request at the
+ * end of each quantum, the request is retired and its memory freed while
+ * the others keep running); lbm_last_error() then names the reason. */
 int lbm_server_poll(lbm_server* s, uint64_t req_id, int* state, double* time_to_solution_s);
 /* Fields / diagnostics of a finished request (as lbm_read_fields/_diag). */
 int lbm_server_read_fields(lbm_server* s, uint64_t req_id, double* rho, double* ux, double* uy,

@@ -19,6 +19,7 @@
  * stated in a comment at the point where it shapes the code.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -667,3 +668,7 @@ void oc_mrt_matrix(double* M81) {
   for (int k = 0; k < 9; ++k)
     for (int i = 0; i < 9; ++i) M81[k * 9 + i] = MRT_M[k][i];
 }
+
+/* OpenMP threads of the per-node loops (timing legs of the CPU baseline). */
+void oc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oc_max_threads(void) { return omp_get_max_threads(); }

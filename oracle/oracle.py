@@ -76,6 +76,8 @@ def lib():
         L.oc_collide_f_node.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, dp]
         L.oc_collide_g_node.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, C.c_double, dp]
         L.oc_mrt_matrix.argtypes = [dp]
+        L.oc_set_threads.argtypes = [C.c_int]
+        L.oc_max_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -362,3 +364,9 @@ def maxwell(T, a=2 / 49, b=2 / 21, R=1.0, omega=0.344):
     psat = brentq(area, p_lo + eps, p_hi - eps, xtol=1e-16, rtol=1e-15, maxiter=500)
     vl, vg = roots(psat)
     return 1.0 / vl, 1.0 / vg, psat
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's per-node loops; returns the count now in use."""
+    lib().oc_set_threads(int(n))
+    return int(lib().oc_max_threads())

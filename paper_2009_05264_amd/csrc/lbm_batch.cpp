@@ -63,36 +63,44 @@ static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int)
   return capture_pairs(s, g, 1, enqueue, ctx);
 }
 
-// Steps per long replay graph.  One hipGraphLaunch costs the host a few
-// microseconds, more than a step of a small domain: replaying two launches
-// per graph left a ~2.5 us gap per step on a 1600x200 channel, a graph of
-// 32 launches none.
-constexpr int kLongPairs = 16;
+// Replay graphs of 2^k launch pairs, k < kGraphLevels.  One hipGraphLaunch
+// costs the host a few microseconds, more than a step of a small domain:
+// replaying two launches per graph left a ~2.5 us gap per step on a
+// 1600x200 channel, a graph of 32 launches none.  Any even step count is
+// replayed as repeats of the longest graph plus at most one graph of each
+// shorter length (its binary digits), so a call of n steps launches at most
+// n / 32 + 4 graphs.
+constexpr int kGraphLevels = 5;
 
-// Replays up to n steps from an even step: long graphs, then pair graphs
-// (captured on first use); *done counts the steps enqueued, and the at most
-// one step left over is the caller's.
-static int replay_steps(hipStream_t s, GraphEntry* pair, GraphEntry* lng, int64_t n,
+// Captures the graphs a call needs (all of them when eager), before any of
+// them is launched: a capture never lands between launches of a call.
+static int ensure_graphs(hipStream_t s, std::vector<GraphEntry>& g, int64_t pairs, bool eager,
+                         int (*enqueue)(void*, int), void* ctx) {
+  if ((int)g.size() < kGraphLevels) g.resize(kGraphLevels);
+  const int top = kGraphLevels - 1;
+  for (int k = 0; k < kGraphLevels; ++k) {
+    const bool needed = k == top ? (pairs >> top) > 0 : ((pairs >> k) & 1) != 0;
+    if (g[k].exec || !(eager || needed)) continue;
+    int rc = capture_pairs(s, &g[k], 1 << k, enqueue, ctx);
+    if (rc) return rc;
+  }
+  return LBM_OK;
+}
+
+// Replays the even part of n steps from an even step; *done counts the
+// steps enqueued (the at most one step left over is the caller's).
+static int replay_steps(hipStream_t s, std::vector<GraphEntry>& g, int64_t n, bool eager,
                         int (*enqueue)(void*, int), void* ctx, int64_t* done) {
   *done = 0;
-  const int64_t nl = n / (2 * kLongPairs);
-  if (nl > 0) {
-    if (!lng->exec) {
-      int rc = capture_pairs(s, lng, kLongPairs, enqueue, ctx);
-      if (rc) return rc;
-    }
-    for (int64_t k = 0; k < nl; ++k) HIPCHECK(hipGraphLaunch(lng->exec, s));
-    *done += nl * 2 * kLongPairs;
-  }
-  const int64_t np = (n - *done) / 2;
-  if (np > 0) {
-    if (!pair->exec) {
-      int rc = capture_pair(s, pair, enqueue, ctx);
-      if (rc) return rc;
-    }
-    for (int64_t k = 0; k < np; ++k) HIPCHECK(hipGraphLaunch(pair->exec, s));
-    *done += 2 * np;
-  }
+  const int64_t pairs = n / 2;
+  if (pairs == 0) return LBM_OK;
+  int rc = ensure_graphs(s, g, pairs, eager, enqueue, ctx);
+  if (rc) return rc;
+  const int top = kGraphLevels - 1;
+  for (int64_t k = 0; k < (pairs >> top); ++k) HIPCHECK(hipGraphLaunch(g[top].exec, s));
+  for (int k = top - 1; k >= 0; --k)
+    if ((pairs >> k) & 1) HIPCHECK(hipGraphLaunch(g[k].exec, s));
+  *done = 2 * pairs;
   return LBM_OK;
 }
 
@@ -104,15 +112,15 @@ static int enqueue_domain_phase(void* ctx, int phase) {
 
 int lbm_run_steps(lbm_domain* d, int64_t n) {
   if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch; step the batch");
-  if (n < 8) return lbm_enqueue_steps(d, n);
-  if ((d->step & 1) && n > 0) {
+  if (n == 0) return ensure_graphs(d->stream, d->graphs, 0, true, enqueue_domain_phase, d);
+  if (n < 2) return lbm_enqueue_steps(d, n);
+  if (d->step & 1) {
     int rc = lbm_enqueue_steps(d, 1);
     if (rc) return rc;
     --n;
   }
-  if (d->graphs.size() < 2) d->graphs.resize(2);
   int64_t done = 0;
-  int rc = replay_steps(d->stream, &d->graphs[0], &d->graphs[1], n, enqueue_domain_phase, d, &done);
+  int rc = replay_steps(d->stream, d->graphs, n, true, enqueue_domain_phase, d, &done);
   d->step += done;
   if (rc) return rc;
   if (n > done) return lbm_enqueue_steps(d, n - done);
@@ -133,10 +141,12 @@ struct lbm_batch {
     int nfins = 0;
   };
   std::vector<Group> groups;
-  GraphEntry graph;       // one launch pair
-  GraphEntry graph_long;  // kLongPairs launch pairs
+  std::vector<GraphEntry> graphs;  // [k]: 2^k launch pairs
+  GraphEntry probe;                // the autotuner's timing graph (one launch pair)
+  bool eager = true;               // capture every replay graph on first use
   int64_t k = 0;  // steps done by the batch
   int rows = kDefaultTileRows;
+  std::vector<int> saved_rows;  // each domain's own rows setting, restored by lbm_batch_destroy
 };
 
 // Tiles of each domain in its own layout, concatenated in the order of the
@@ -176,12 +186,16 @@ static int enqueue_batch_phase(void* ctx, int phase) {
   return LBM_OK;
 }
 
+static void drop_graph(GraphEntry* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  *g = GraphEntry{};
+}
+
 static void drop_batch_graph(lbm_batch* b) {
-  for (GraphEntry* g : {&b->graph, &b->graph_long}) {
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
-    *g = GraphEntry{};
-  }
+  for (auto& g : b->graphs) drop_graph(&g);
+  b->graphs.clear();
+  drop_graph(&b->probe);
 }
 
 // Without the autotuner, the domains on automatic rows get one tile height
@@ -255,14 +269,14 @@ static int time_config(lbm_batch* b, int reps, float* ms) {
     int rc = batch_steps_plain(b, 1);
     if (rc) return rc;
   }
-  int rc = capture_pair(b->stream, &b->graph, enqueue_batch_phase, b);
+  int rc = capture_pair(b->stream, &b->probe, enqueue_batch_phase, b);
   if (rc) return rc;
-  HIPCHECK(hipGraphLaunch(b->graph.exec, b->stream));  // warm-up pair
+  HIPCHECK(hipGraphLaunch(b->probe.exec, b->stream));  // warm-up pair
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   HIPCHECK(hipEventRecord(e0, b->stream));
-  for (int r = 0; r < reps; ++r) HIPCHECK(hipGraphLaunch(b->graph.exec, b->stream));
+  for (int r = 0; r < reps; ++r) HIPCHECK(hipGraphLaunch(b->probe.exec, b->stream));
   HIPCHECK(hipEventRecord(e1, b->stream));
   HIPCHECK(hipEventSynchronize(e1));
   float t = 0;
@@ -345,37 +359,50 @@ extern "C" int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune
   lbm_batch* b = new lbm_batch();
   b->stream = doms[0]->stream;
   for (int i = 0; i < n; ++i) {
-    HIPCHECK(hipStreamSynchronize(doms[i]->stream));
+    hipError_t e = hipStreamSynchronize(doms[i]->stream);
+    if (e != hipSuccess) {
+      delete b;
+      return lbm_fail(LBM_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
     b->doms.push_back(doms[i]);
+    b->saved_rows.push_back(doms[i]->rows);
   }
+  int rc = LBM_OK;
   for (lbm_domain* d : b->doms) {
     d->in_batch = true;
     d->batch_stream = b->stream;
     d->host.parity = (int)(d->step & 1);
-    HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
+    hipError_t e = hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice);
+    if (e != hipSuccess && !rc) rc = lbm_fail(LBM_E_DEVICE, "descriptor upload: %s", hipGetErrorString(e));
   }
-  int rc = build_groups(b);
+  if (!rc) rc = build_groups(b);
   if (!rc && tune_cache_json) rc = autotune(b, tune_cache_json[0] ? tune_cache_json : nullptr);
   else if (!rc) rc = batch_auto_rows(b);
   if (rc) {
+    const std::string msg = lbm_last_error();
     lbm_batch_destroy(b);
-    return rc;
+    return lbm_fail(rc, "%s", msg.c_str());
   }
   *out = b;
   return LBM_OK;
 }
 
+void lbm_batch_lazy_graphs(lbm_batch* b) {
+  if (b) b->eager = false;
+}
+
 extern "C" int lbm_batch_step(lbm_batch* b, int64_t n) {
   if (!b) return lbm_fail(LBM_E_INVALID, "batch is NULL");
   if (n < 0) return lbm_fail(LBM_E_INVALID, "nsteps must be >= 0");
-  if (n < 8) return batch_steps_plain(b, n);
+  if (n == 0) return ensure_graphs(b->stream, b->graphs, 0, true, enqueue_batch_phase, b);
+  if (n < 2) return batch_steps_plain(b, n);
   if (b->k & 1) {
     int rc = batch_steps_plain(b, 1);
     if (rc) return rc;
     --n;
   }
   int64_t done = 0;
-  int rc = replay_steps(b->stream, &b->graph, &b->graph_long, n, enqueue_batch_phase, b, &done);
+  int rc = replay_steps(b->stream, b->graphs, n, b->eager, enqueue_batch_phase, b, &done);
   b->k += done;
   for (lbm_domain* d : b->doms) d->step += done;
   if (rc) return rc;
@@ -398,15 +425,18 @@ extern "C" int lbm_batch_destroy(lbm_batch* b) {
     if (g.fins_d) (void)hipFree(g.fins_d);
   }
   int rc = LBM_OK;
-  for (lbm_domain* d : b->doms) {
+  for (size_t i = 0; i < b->doms.size(); ++i) {
+    lbm_domain* d = b->doms[i];
     d->in_batch = false;
     d->batch_stream = nullptr;
     d->host.parity = 0;
     (void)hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice);
-    if (d->batch_rows) {
-      // back to the domain's own automatic rows (pending sums carried over)
+    const int own = i < b->saved_rows.size() ? b->saved_rows[i] : d->rows;
+    if (d->batch_rows || d->rows != own) {
+      // back to the domain's own rows (the batch height or the autotuner's
+      // choice undone; pending sums carried over)
       d->batch_rows = 0;
-      const int r = lbm_set_tile_rows(d, d->rows);
+      const int r = lbm_set_tile_rows(d, own);
       if (r && rc == LBM_OK) rc = r;
     }
   }

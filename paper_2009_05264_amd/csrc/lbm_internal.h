@@ -10,6 +10,10 @@ constexpr int kStripInterior = 60;  // interior columns per wave (64 - 2 - 2 hal
 constexpr int kPartials = 8;        // doubles per tile partial
 constexpr int kRing = 4096;         // per-step diagnostics records kept on device
 constexpr int kFin = 16;            // finalizer waves per domain (level-1 slices)
+constexpr int kAccSlots = 16;       // fixed-point mass accumulators per domain and parity
+constexpr int kAccStride = 16;      // 64-bit words between slots: one 128-byte line each
+// fixed-point scale of the mass accumulators: 2^32 units per unit density
+constexpr double kMassScale = 4294967296.0;
 
 // Partial sums of one tile, in this order.
 enum { P_MASS = 0, P_ENERGY, P_HEATQ, P_VAPOR, P_CLAMP, P_NONFINITE, P_PIN, P_POUT };
@@ -29,7 +33,7 @@ struct DevDomain {
   int ntiles, pad0;
   // EOS / force constants
   float a, b, R, kappa;
-  float pad7, Tc, beta, c0g2;     // c0g2 = 2 / (c0 g)
+  float kw, Tc, beta, c0g2;       // c0g2 = 2 / (c0 g); kw = G_wet / (18 g): Eq. 15 as G_wet w_i = kw G_i
   float G1, G2, half_1mb, pad1;    // half_1mb = (1 - beta) / 2
   // collision
   float s_e, s_eps, s_q, s_nu;
@@ -50,6 +54,14 @@ struct DevDomain {
   const int* heater;    // bottom heater flags [nx]
   double* partials[2];  // [kPartials][pstride] per launch parity (SoA over tiles)
   double* l1[2];        // [kFin][kPartials] slice sums of the partials, per parity
+  // Mean density of the previous state for the buoyancy force (Eq. 14):
+  // each launch adds its exact fixed-point mass into macc[parity] (running
+  // totals, kAccSlots slots); a tile reads the totals of the other parity
+  // and keeps them in mhist[parity][tile], so the difference from its
+  // previous reading is the mass of the state one launch back.
+  unsigned long long* macc[2];   // [kAccSlots * kAccStride] per parity (slot k at k * kAccStride)
+  unsigned long long* mhist[2];  // [pstride] per parity
+  int* nf_flag;         // set to 1 by a step that meets a non-finite density or temperature
   double* rbar;         // scratch for read-out reductions
   DiagRec* ring;        // [kRing]
   long long* step_dev;  // device step counter (written only by the first tile)
@@ -96,4 +108,5 @@ hipError_t lbm_launch_finalize(const double* partials, int pstride, int ntiles, 
 hipError_t lbm_launch_init(int storage, lbm::DevDomain* dhost_copy_dev, const lbm::DevDomain& dh,
                            const double* rho0, const double* T0, double rho_u, double T_u,
                            double noise, unsigned long long seed, int buf_index, hipStream_t s);
+hipError_t lbm_launch_init_aux(lbm::DevDomain* dev, double mass0, hipStream_t s);
 hipError_t lbm_launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -18,12 +18,18 @@
 // FP16 or BF16 (template parameter), one plane per direction holding the
 // (f_i, g_i) pair of every node (f_i alone for isothermal domains).
 //
-// Reductions for the diagnostics and for the mean density of the buoyancy
-// force are fixed-order FP64: each tile writes its partial sums; in the next
-// launch kFin finalizer waves per domain reduce slices of them, and the
-// launch after that sums the slices (kernel boundaries order every step).
+// Reductions for the diagnostics are fixed-order FP64: each tile writes its
+// partial sums; in the next launch kFin finalizer waves per domain reduce
+// slices of them, and the launch after that sums the slices (kernel
+// boundaries order every step).  The mean density of the buoyancy force
+// (Eq. 14) is that of the previous state: every tile adds the exact
+// fixed-point mass of its nodes into running totals with integer atomics
+// (order-free, so bitwise reproducible), and the next launch's tiles read
+// the totals and subtract their own previous reading.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "../../include/lbmflow.h"
 #include "lbm_internal.h"
@@ -367,6 +373,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum of v over lanes 0-15 (an inclusive scan along the first DPP row,
+// whose last lane then holds the total), returned to every lane.
+__device__ __forceinline__ unsigned long long row0_sum_u64(unsigned long long v) {
+  auto shr = [](unsigned long long x, auto ctrl) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, decltype(ctrl)::value, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), decltype(ctrl)::value, 0xF, 0xF, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+  };
+  v += shr(v, std::integral_constant<int, 0x111>{});  // row_shr:1
+  v += shr(v, std::integral_constant<int, 0x112>{});  // row_shr:2
+  v += shr(v, std::integral_constant<int, 0x114>{});  // row_shr:4
+  v += shr(v, std::integral_constant<int, 0x118>{});  // row_shr:8
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 15);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 15);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Fixed-point form (2^32 units) of a tile's mass sum; non-finite or absurd
+// sums (a diverged run, flagged by the non-finite count) contribute zero.
+__device__ __forceinline__ unsigned long long to_fixed(double m) {
+  return (unsigned long long)(long long)(fabs(m) < 1e9 ? m * kMassScale : 0.0);
+}
+
 __device__ __forceinline__ int wave_sum_int(int v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
@@ -428,7 +457,7 @@ struct TileRun {
   int pitch, sst[9];  // plane byte offsets
   int kb;             // extra base offset of the pull resource (column-edge tiles)
   float gbar;     // rho_ref - mean density (formed in run(), first used by stage 2)
-  double mpart;   // this lane's level-1 mass slice
+  unsigned long long mtot, mprev;  // running mass totals: one slot per lane; this tile's previous reading
   int r_end;
   // boundary tiles: -1 in lanes whose column is 0 (mL) / nx-1 (mR)
   int mL = 0, mR = 0;
@@ -440,6 +469,7 @@ struct TileRun {
   Rsrc rfo, rfd;  // outlet memory, this launch's source and destination
   // reductions
   double acc_mass = 0.0, acc_energy = 0.0, acc_q = 0.0, acc_pin = 0.0, acc_pout = 0.0;
+  double mass_tile = 0.0;  // wave total of acc_mass once the tile's rows are in (stepping)
   int acc_vap = 0, acc_clamp = 0, acc_nf = 0;
   // prefetched rows in NB rotating buffers: the loads of row r + NB - 1 are
   // issued while row r is consumed, so a loaded register is first touched
@@ -488,10 +518,13 @@ struct TileRun {
     kb = XE && TH ? 2 * sst[1] : 0;
     rs = make_rsrc((const char*)D.buf[phase] - kb - (pitch + 1) * E2);
     rd = make_rsrc(D.buf[phase ^ 1]);
-    // mean density two states back: the level-1 slices written by the
-    // previous launch's finalizers, summed in run() once the first rows are
-    // in flight
-    mpart = lane < kFin ? D.l1[phase][lane * kPartials + P_MASS] : 0.0;
+    // mean density of the previous state: the running mass totals the
+    // previous launch added to (one slot per lane) and this tile's reading
+    // of them two launches back, combined in run() once the first rows are
+    // in flight.  Plain loads: both were last written in earlier launches,
+    // whose writes the kernel boundary makes visible.
+    mtot = lane < kAccSlots ? D.macc[phase ^ 1][lane * kAccStride] : 0ull;
+    mprev = D.mhist[phase ^ 1][tl.local];
     r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) bh[i] = bk[i] = ck[i] = fc[i] = 0.f;
@@ -529,6 +562,18 @@ struct TileRun {
       const int oH = walls && tl.y0 == 0 ? xc * 4 : kDrop;
       heat = __builtin_amdgcn_raw_buffer_load_b32(make_rsrc(D.heater), oH, 0, 0) != 0u;
     }
+  }
+
+  // this state's mass for the next launch's buoyancy: each lane's FP64 sum
+  // of FP32 densities is exact, and so is the tile's FP64 total (at most 64
+  // x ~2^14 with a 2^-32 grain for densities above 2^-9), so the fixed-point
+  // total is exact and tiling-independent
+  __device__ __forceinline__ void flush_mass() {
+    mass_tile = wave_sum(acc_mass);
+    const unsigned long long m = to_fixed(mass_tile);
+    if (lane == 0)
+      __hip_atomic_fetch_add(&D.macc[phase][(tl.local & (kAccSlots - 1)) * kAccStride], m, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
   }
 
   static __device__ __forceinline__ float ld32(Rsrc r, int voff) {
@@ -694,10 +739,12 @@ struct TileRun {
     }
     int fo_off = kDrop;  // outlet memory store of this row
     if (sa) {
+      // a solid cell enters only the adhesion sum of Eq. 15:
+      // -G_wet psi(x) w_i psi_w c_i = -psi(x) (kw G_i) psi_w c_i
       const float psiW = r < 0 ? psiS : psiN;
       a_psi = psiW;
-      a_A = D.beta * psiW;
-      a_B = psiW * psiW;
+      a_A = D.kw * psiW;
+      a_B = 0.f;
     } else {
       const int ry = (!EDGE || walls) ? r : wrap1(r, ny);
       if (EDGE) fix_row(ry, ah, ak, pfo[B]);
@@ -887,6 +934,10 @@ struct TileRun {
   __device__ __forceinline__ void steady(int r) {
     const int r_out = MODE == MODE_STEP ? r_end - 1 : r_end;  // last row-r with stage-2 output
     for (; r + NB - 1 <= r_out; r += NB) trip<B0, NB>(r);
+    // rows before r (y1 - 1, the tile's last own row, among them) have their
+    // moments: hand the mass to the next launch now, so the atomic's round
+    // trip overlaps the remaining iterations
+    if (MODE == MODE_STEP) flush_mass();
     tail<B0, 0>(r, r_out - r + 1);
   }
 
@@ -901,7 +952,13 @@ struct TileRun {
     if constexpr (NB >= 4) fetch<2>(y0);
     iter<false, false, false, true, 0>(y0 - 2);
     iter<false, false, false, true, 1 % NB>(y0 - 1);
-    gbar = (float)((double)D.rho_ref - wave_sum(mpart) / ((double)nx * (double)ny));
+    {
+      static_assert(kAccSlots == 16, "the slots are summed along one DPP row");
+      const unsigned long long tot = row0_sum_u64(mtot);
+      if (MODE == MODE_STEP && lane == 0) D.mhist[phase ^ 1][tl.local] = tot;  // read back two launches on
+      const double mass = (double)(long long)(tot - mprev) * (1.0 / kMassScale);
+      gbar = (float)((double)D.rho_ref - mass / ((double)nx * (double)ny));
+    }
     iter<true, false, false, true, 2 % NB>(y0);
     iter<true, true, false, true, 3 % NB>(y0 + 1);
     steady<4 % NB>(y0 + 2);
@@ -909,7 +966,7 @@ struct TileRun {
     // exact 32-bit integers; heater and pressure sums are zero off the edge
     // tiles (fewer cross-lane rounds at the end of every tile)
     double v[kPartials];
-    v[P_MASS] = wave_sum(acc_mass);
+    v[P_MASS] = MODE == MODE_STEP ? mass_tile : wave_sum(acc_mass);
     v[P_ENERGY] = wave_sum(acc_energy);
     v[P_VAPOR] = (double)wave_sum_int(acc_vap);
     v[P_CLAMP] = (double)wave_sum_int(acc_clamp);
@@ -922,6 +979,8 @@ struct TileRun {
 #pragma unroll
       for (int q = 0; q < kPartials; ++q) out[(long long)q * D.pstride] = v[q];
     }
+    if (MODE == MODE_STEP && lane == 0 && v[P_NONFINITE] > 0.0) *D.nf_flag = 1;  // sticky, for the server
+    v[P_MASS] = MODE == MODE_STEP ? mass_tile : wave_sum(acc_mass);
   }
 };
 
@@ -1057,6 +1116,39 @@ __global__ void init_kernel(DevDomain D, const double* rho0, const double* T0, d
   }
 }
 
+// Reduction state of a freshly initialised domain (one block): the running
+// mass totals give the first state's buoyancy the mean initial density
+// (mass0 / nodes; the first launch, parity 0, reads parity 1), every tile's
+// last reading is zero, the pending diagnostics sums of the "previous"
+// launches hold the initial mass, the step counter and the non-finite flag
+// are zero and the per-step records are empty (step -1).
+__global__ __launch_bounds__(256) void init_aux_kernel(DevDomain* D, double mass0) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const unsigned long long m0 = (unsigned long long)(long long)llrint(mass0 * kMassScale);
+  for (int k = t; k < kAccSlots * kAccStride; k += nt) {
+    D->macc[0][k] = 0ull;
+    D->macc[1][k] = k == 0 ? m0 : 0ull;
+  }
+  for (int k = t; k < D->pstride; k += nt) {
+    D->mhist[0][k] = 0ull;
+    D->mhist[1][k] = 0ull;
+  }
+  for (int k = t; k < kPartials * D->pstride; k += nt) D->partials[1][k] = k == P_MASS * D->pstride ? mass0 : 0.0;
+  for (int k = t; k < kFin * kPartials; k += nt) {
+    D->l1[0][k] = k == P_MASS ? mass0 : 0.0;
+    D->l1[1][k] = k == P_MASS ? mass0 : 0.0;
+  }
+  for (int k = t; k < kRing; k += nt) {
+    D->ring[k].step = -1;
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) D->ring[k].v[q] = __builtin_nan("");
+  }
+  if (t == 0) {
+    *D->step_dev = 0;
+    *D->nf_flag = 0;
+  }
+}
+
 // Streaming copy: each block moves one contiguous chunk of chunk 16-byte
 // elements, four loads in flight per thread before their stores.  Whole
 // chunks per block keep each DRAM page's traffic together, which measured
@@ -1127,6 +1219,11 @@ hipError_t lbm_launch_init(int storage, DevDomain*, const DevDomain& dh, const d
 #define L(SS) hipLaunchKernelGGL((init_kernel<SS>), dim3(grid), dim3(block), 0, s, dh, rho0, T0, rho_u, T_u, noise, seed, b)
   DISPATCH_STORE(storage, L)
 #undef L
+  return hipGetLastError();
+}
+
+hipError_t lbm_launch_init_aux(DevDomain* dev, double mass0, hipStream_t s) {
+  hipLaunchKernelGGL(init_aux_kernel, dim3(1), dim3(256), 0, s, dev, mass0);
   return hipGetLastError();
 }
 

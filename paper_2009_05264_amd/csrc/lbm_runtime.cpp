@@ -97,6 +97,8 @@ int validate(const lbm_params* p) {
     return lbm_fail(LBM_E_INVALID, "temperatures must be positive");
   if (!(p->a > 0) || !(p->b > 0) || !(p->R > 0) || !(p->c0 > 0) || p->g == 0)
     return lbm_fail(LBM_E_INVALID, "EOS constants out of range");
+  if (!std::isfinite(p->G_wet) || !std::isfinite(p->beta))
+    return lbm_fail(LBM_E_INVALID, "G_wet and beta must be finite");
   if (p->bc_x != LBM_BCX_PERIODIC && p->nx < 3)
     return lbm_fail(LBM_E_INVALID, "a channel needs nx >= 3");
   if (p->bc_x == LBM_BCX_CHANNEL_P && !(p->rho_out > 0))
@@ -120,7 +122,8 @@ int validate(const lbm_params* p) {
 namespace {
 
 struct Layout {
-  size_t state, fold, psiw, Tw, heater, partials, rpart, l1, rbar, ring, stepc, out, desc, self, tiles, total;
+  size_t state, fold, psiw, Tw, heater, partials, rpart, l1, macc, mhist, rbar, nff, ring, stepc, out, desc, self,
+      tiles, total;
   size_t state_bytes, fold_bytes;
 };
 
@@ -149,7 +152,10 @@ Layout layout_of(const lbm_params& p) {
   L.partials = o; o += 2 * align_up(mt * kPartials * sizeof(double), 256);
   L.rpart = o; o += align_up(mt * kPartials * sizeof(double), 256);
   L.l1 = o; o += 2 * align_up(kFin * kPartials * sizeof(double), 256);
+  L.macc = o; o += 2 * align_up(kAccSlots * kAccStride * sizeof(unsigned long long), 256);
+  L.mhist = o; o += 2 * align_up(mt * sizeof(unsigned long long), 256);
   L.rbar = o; o += 256;
+  L.nff = o; o += 256;
   L.ring = o; o += align_up(kRing * sizeof(DiagRec), 256);
   L.stepc = o; o += 256;
   L.out = o; o += 4 * align_up((size_t)p.nx * p.ny * sizeof(float), 256);
@@ -163,6 +169,13 @@ Layout layout_of(const lbm_params& p) {
 }  // namespace
 
 // ------------------------------------------------------------------ API
+extern "C" double lbm_neutral_G_wet(const lbm_params* p) {
+  // A flat wall removes the solid neighbours from both sums of Eq. 9, whose
+  // missing pull is (1 + beta)/2 sum_solid G_i psi^2 c_i; with G_i = 18 g w_i
+  // (Eq. 10 on D2Q9) Eq. 15 returns it exactly when G_wet = 9 g (1 + beta).
+  return p ? 9.0 * p->g * (1.0 + p->beta) : 0.0;
+}
+
 extern "C" int lbm_params_default(lbm_params* p) {
   if (!p) return lbm_fail(LBM_E_INVALID, "params is NULL");
   memset(p, 0, sizeof(*p));
@@ -195,6 +208,7 @@ extern "C" int lbm_params_default(lbm_params* p) {
   p->rho_out = 6.4989457632878835;
   p->rho_ref = 0.0;
   p->T_ref = 0.0;
+  p->G_wet = lbm_neutral_G_wet(p);
   return LBM_OK;
 }
 
@@ -229,6 +243,8 @@ void fill_desc(lbm_domain* d) {
   D.kappa = (float)kappa_of(p);
   D.Tc = (float)Tc;
   D.beta = (float)p.beta;
+  // Eq. 15 with G_i = 18 g w_i (Eq. 10 on D2Q9): G_wet w_i = (G_wet / 18 g) G_i
+  D.kw = (float)(p.G_wet / (18.0 * p.g));
   D.c0g2 = (float)(2.0 / (p.c0 * p.g));
   D.G1 = (float)(2.0 * p.g);
   D.G2 = (float)(0.5 * p.g);
@@ -282,6 +298,7 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
       d->simds = 4 * cus;
   }
+  (void)hipGetDevice(&d->device);
   if (hip_stream) {
     d->stream = (hipStream_t)hip_stream;
     d->own_stream = false;
@@ -332,7 +349,14 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   const size_t l1b = align_up(kFin * kPartials * sizeof(double), 256);
   D.l1[0] = (double*)(m + L.l1);
   D.l1[1] = (double*)(m + L.l1 + l1b);
+  const size_t ab = align_up(kAccSlots * kAccStride * sizeof(unsigned long long), 256);
+  D.macc[0] = (unsigned long long*)(m + L.macc);
+  D.macc[1] = (unsigned long long*)(m + L.macc + ab);
+  const size_t hb = align_up(max_tiles(*p) * sizeof(unsigned long long), 256);
+  D.mhist[0] = (unsigned long long*)(m + L.mhist);
+  D.mhist[1] = (unsigned long long*)(m + L.mhist + hb);
   D.rbar = (double*)(m + L.rbar);
+  D.nf_flag = (int*)(m + L.nff);
   D.ring = (DiagRec*)(m + L.ring);
   D.step_dev = (long long*)(m + L.stepc);
   const size_t ob = align_up((size_t)p->nx * p->ny * sizeof(float), 256);
@@ -424,59 +448,84 @@ extern "C" int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, 
   return LBM_OK;
 }
 
-extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_u,
-                               double T_u, double noise, uint64_t seed) {
+// Every tile's last reading of the running mass totals, per parity (all
+// tiles hold the same value; set after a retiling or a load).
+hipError_t fill_mhist(lbm_domain* d, unsigned long long h0, unsigned long long h1) {
+  const size_t n = (size_t)d->host.pstride;
+  std::vector<unsigned long long> v(n, h0);
+  hipError_t e = hipMemcpyAsync(d->host.mhist[0], v.data(), n * sizeof(v[0]), hipMemcpyHostToDevice, d->stream);
+  if (e != hipSuccess) return e;
+  std::fill(v.begin(), v.end(), h1);
+  e = hipMemcpyAsync(d->host.mhist[1], v.data(), n * sizeof(v[0]), hipMemcpyHostToDevice, d->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(d->stream);
+}
+
+namespace {
+
+// Checks of lbm_init_fields and the FP64 mass of the initial density (fixed
+// order), which the first state's buoyancy uses as its mean.
+int init_args(lbm_domain* d, const double* rho0, const double* T0, double rho_u, double T_u, double noise,
+              uint64_t seed, double* sum) {
   if (!d) return lbm_fail(LBM_E_INVALID, "domain is NULL");
   if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch");
-  const int nx = d->P.nx, ny = d->P.ny;
-  const size_t n = (size_t)nx * ny;
   if (!rho0 && !(rho_u > 0)) return lbm_fail(LBM_E_INVALID, "rho_uniform must be positive");
   if (!T0 && !(T_u > 0)) return lbm_fail(LBM_E_INVALID, "T_uniform must be positive");
-  double* rd = nullptr;
-  double* td = nullptr;
-  // mean of the initial density (FP64, fixed order)
-  double sum = 0.0;
+  const int nx = d->P.nx, ny = d->P.ny;
+  const size_t n = (size_t)nx * ny;
+  double s = 0.0;
   if (rho0) {
-    for (size_t i = 0; i < n; ++i) sum += rho0[i];
+    for (size_t i = 0; i < n; ++i) s += rho0[i];
   } else {
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const unsigned long long z = splitmix64_host(seed ^ (unsigned long long)((long long)y * nx + x));
         const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
-        sum += rho_u * (1.0 + noise * (2.0 * u - 1.0));
+        s += rho_u * (1.0 + noise * (2.0 * u - 1.0));
       }
   }
-  if (rho0) {
-    HIPCHECK(hipMalloc(&rd, n * sizeof(double)));
-    HIPCHECK(hipMemcpy(rd, rho0, n * sizeof(double), hipMemcpyHostToDevice));
-  }
-  if (T0) {
-    HIPCHECK(hipMalloc(&td, n * sizeof(double)));
-    HIPCHECK(hipMemcpy(td, T0, n * sizeof(double), hipMemcpyHostToDevice));
-  }
+  *sum = s;
+  return LBM_OK;
+}
+
+// The initial state from device copies of the optional arrays (staged by
+// the caller of this function), then the reduction state; waits for it.
+int init_on_device(lbm_domain* d, const double* rd, const double* td, double rho_u, double T_u, double noise,
+                   uint64_t seed, double sum) {
   d->host.parity = 0;
   HIPCHECK(hipMemcpyAsync(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice, d->stream));
   HIPCHECK(lbm_launch_init(d->P.storage, d->dev, d->host, rd, td, rho_u, T_u, noise, seed, 0, d->stream));
-  // lagged means and the partial sums the first step finalizes
-  // pending reductions of the "previous" launches: both level-1 arrays and
-  // the partial sums the first launch's finalizers read hold the initial mass
-  std::vector<double> l1(kFin * kPartials, 0.0);
-  l1[P_MASS] = sum;
-  HIPCHECK(hipMemcpyAsync(d->host.l1[0], l1.data(), l1.size() * sizeof(double), hipMemcpyHostToDevice, d->stream));
-  HIPCHECK(hipMemcpyAsync(d->host.l1[1], l1.data(), l1.size() * sizeof(double), hipMemcpyHostToDevice, d->stream));
-  std::vector<double> parts((size_t)d->host.pstride * kPartials, 0.0);
-  parts[(size_t)P_MASS * d->host.pstride] = sum;
-  HIPCHECK(hipMemcpyAsync(d->host.partials[1], parts.data(), parts.size() * sizeof(double),
-                          hipMemcpyHostToDevice, d->stream));
-  long long zero = 0;
-  HIPCHECK(hipMemcpyAsync(d->host.step_dev, &zero, sizeof(zero), hipMemcpyHostToDevice, d->stream));
-  HIPCHECK(hipMemsetAsync(d->host.ring, 0xFF, kRing * sizeof(DiagRec), d->stream));
+  HIPCHECK(lbm_launch_init_aux(d->dev, sum, d->stream));
   HIPCHECK(hipStreamSynchronize(d->stream));
-  if (rd) (void)hipFree(rd);
-  if (td) (void)hipFree(td);
   d->step = 0;
   d->inited = true;
   return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_u,
+                               double T_u, double noise, uint64_t seed) {
+  double sum = 0.0;
+  int rc = init_args(d, rho0, T0, rho_u, T_u, noise, seed, &sum);
+  if (rc) return rc;
+  const size_t bytes = (size_t)d->P.nx * d->P.ny * sizeof(double);
+  // device staging of the host arrays, freed before returning
+  double* stage[2] = {nullptr, nullptr};
+  const double* src[2] = {rho0, T0};
+  for (int k = 0; k < 2 && !rc; ++k) {
+    if (!src[k]) continue;
+    if (hipMalloc(&stage[k], bytes) != hipSuccess) {
+      stage[k] = nullptr;
+      rc = lbm_fail(LBM_E_NOMEM, "hipMalloc of %zu staging bytes failed", bytes);
+    } else if (hipMemcpy(stage[k], src[k], bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = lbm_fail(LBM_E_DEVICE, "upload of the initial fields failed");
+    }
+  }
+  if (!rc) rc = init_on_device(d, stage[0], stage[1], rho_u, T_u, noise, seed, sum);
+  for (double* p : stage)
+    if (p) (void)hipFree(p);
+  return rc;
 }
 
 int lbm_enqueue_steps(lbm_domain* d, int64_t nsteps) {
@@ -593,36 +642,72 @@ extern "C" int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n) {
 
 // ------------------------------------------------------------------ checkpoints
 namespace {
+// A checkpoint holds the state the next step reads, independent of the
+// tiling: state buffer, outlet memory, the pending diagnostics reductions
+// (per-tile partials summed into totals), the level-1 slices, the device
+// step counter, the running mass totals and the tiles' common last reading.
 struct CkptHeader {
   char magic[8];
   int32_t nx, ny, storage, isothermal;
   int64_t step;
-  uint64_t state_bytes, fold_bytes, part_bytes;
+  uint64_t state_bytes, fold_bytes;
 };
+struct CkptTail {
+  double part_tot[kPartials];
+  double l1[2][kFin * kPartials];
+  long long step_dev;
+  unsigned long long macc[2][kAccSlots * kAccStride];
+  unsigned long long mhist[2];
+};
+
+// Totals of the pending per-tile partial sums (parity q), host side.
+int partial_totals(lbm_domain* d, int q, double tot[kPartials]) {
+  const size_t stride = d->host.pstride;
+  std::vector<double> part(stride * kPartials);
+  HIPCHECK(hipMemcpy(part.data(), d->host.partials[q], part.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int k = 0; k < kPartials; ++k) {
+    tot[k] = 0.0;
+    for (int t = 0; t < d->ntiles; ++t) tot[k] += part[(size_t)k * stride + t];
+  }
+  return LBM_OK;
+}
+
+// Pending partial sums of parity q replaced by their totals in tile 0.
+int put_partial_totals(lbm_domain* d, int q, const double tot[kPartials]) {
+  const size_t stride = d->host.pstride;
+  std::vector<double> part(stride * kPartials, 0.0);
+  for (int k = 0; k < kPartials; ++k) part[(size_t)k * stride] = tot[k];
+  HIPCHECK(hipMemcpy(d->host.partials[q], part.data(), part.size() * sizeof(double), hipMemcpyHostToDevice));
+  return LBM_OK;
+}
 }  // namespace
 
 extern "C" int lbm_save(lbm_domain* d, const char* path) {
   if (!d || !path) return lbm_fail(LBM_E_INVALID, "NULL argument");
   if (!d->inited) return lbm_fail(LBM_E_STATE, "nothing to save");
   const Layout L = layout_of(d->P);
-  const int ph = (int)(d->step & 1);
-  const size_t pb = (size_t)d->host.pstride * kPartials * sizeof(double);
-  std::vector<char> st(L.state_bytes), fo(L.fold_bytes), pa(pb);
-  double rb[2 * kFin * kPartials];
-  long long sd;
   HIPCHECK(wait_batch(d));
   HIPCHECK(hipStreamSynchronize(d->stream));
+  // the state of step s lives in buffer s & 1 (alone or in a batch)
+  const int ph = (int)(d->step & 1);
+  std::vector<char> st(L.state_bytes), fo(L.fold_bytes);
+  CkptTail t{};
   HIPCHECK(hipMemcpy(st.data(), d->host.buf[ph], L.state_bytes, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(fo.data(), d->host.fold[ph], L.fold_bytes, hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(pa.data(), d->host.partials[ph ^ 1], pb, hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(rb, d->host.l1[ph], kFin * kPartials * sizeof(double), hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(rb + kFin * kPartials, d->host.l1[ph ^ 1], kFin * kPartials * sizeof(double),
-                     hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(&sd, d->host.step_dev, sizeof(sd), hipMemcpyDeviceToHost));
+  int rc = partial_totals(d, ph ^ 1, t.part_tot);
+  if (rc) return rc;
+  // stored in the order of the step parity (index 0: the next step's own)
+  for (int k = 0; k < 2; ++k) {
+    const int q = ph ^ k;
+    HIPCHECK(hipMemcpy(t.l1[k], d->host.l1[q], sizeof(t.l1[k]), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(t.macc[k], d->host.macc[q], sizeof(t.macc[k]), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(&t.mhist[k], d->host.mhist[q], sizeof(t.mhist[k]), hipMemcpyDeviceToHost));
+  }
+  HIPCHECK(hipMemcpy(&t.step_dev, d->host.step_dev, sizeof(t.step_dev), hipMemcpyDeviceToHost));
   FILE* f = fopen(path, "wb");
   if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s for writing", path);
   CkptHeader h{};
-  memcpy(h.magic, "LBMCKPT3", 8);
+  memcpy(h.magic, "LBMCKPT4", 8);
   h.nx = d->P.nx;
   h.ny = d->P.ny;
   h.storage = d->P.storage;
@@ -630,10 +715,8 @@ extern "C" int lbm_save(lbm_domain* d, const char* path) {
   h.step = d->step;
   h.state_bytes = L.state_bytes;
   h.fold_bytes = L.fold_bytes;
-  h.part_bytes = pb;
   bool ok = fwrite(&h, sizeof(h), 1, f) == 1 && fwrite(st.data(), 1, st.size(), f) == st.size() &&
-            fwrite(fo.data(), 1, fo.size(), f) == fo.size() && fwrite(pa.data(), 1, pa.size(), f) == pa.size() &&
-            fwrite(rb, sizeof(rb), 1, f) == 1 && fwrite(&sd, sizeof(sd), 1, f) == 1;
+            fwrite(fo.data(), 1, fo.size(), f) == fo.size() && fwrite(&t, sizeof(t), 1, f) == 1;
   ok = (fclose(f) == 0) && ok;
   return ok ? LBM_OK : lbm_fail(LBM_E_INVALID, "write to %s failed", path);
 }
@@ -645,33 +728,49 @@ extern "C" int lbm_load(lbm_domain* d, const char* path) {
   if (!f) return lbm_fail(LBM_E_INVALID, "cannot open %s", path);
   CkptHeader h{};
   const Layout L = layout_of(d->P);
-  const size_t pb = (size_t)d->host.pstride * kPartials * sizeof(double);
-  if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "LBMCKPT3", 8) != 0 || h.nx != d->P.nx ||
+  if (fread(&h, sizeof(h), 1, f) != 1 || memcmp(h.magic, "LBMCKPT4", 8) != 0 || h.nx != d->P.nx ||
       h.ny != d->P.ny || h.storage != d->P.storage || h.isothermal != d->P.isothermal ||
-      h.state_bytes != L.state_bytes || h.fold_bytes != L.fold_bytes || h.part_bytes != pb) {
+      h.state_bytes != L.state_bytes || h.fold_bytes != L.fold_bytes) {
     fclose(f);
-    return lbm_fail(LBM_E_INVALID, "%s does not match this domain (geometry, storage or tiling)", path);
+    return lbm_fail(LBM_E_INVALID, "%s does not match this domain (geometry or storage)", path);
   }
-  std::vector<char> st(L.state_bytes), fo(L.fold_bytes), pa(pb);
-  double rb[2 * kFin * kPartials];
-  long long sd;
+  std::vector<char> st(L.state_bytes), fo(L.fold_bytes);
+  CkptTail t{};
   bool ok = fread(st.data(), 1, st.size(), f) == st.size() && fread(fo.data(), 1, fo.size(), f) == fo.size() &&
-            fread(pa.data(), 1, pa.size(), f) == pa.size() && fread(rb, sizeof(rb), 1, f) == 1 &&
-            fread(&sd, sizeof(sd), 1, f) == 1;
+            fread(&t, sizeof(t), 1, f) == 1;
   fclose(f);
   if (!ok) return lbm_fail(LBM_E_INVALID, "%s is truncated", path);
+  HIPCHECK(hipStreamSynchronize(d->stream));
   d->step = h.step;
   d->host.parity = 0;
   HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
   const int ph = (int)(d->step & 1);
   HIPCHECK(hipMemcpy(d->host.buf[ph], st.data(), L.state_bytes, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(d->host.fold[ph], fo.data(), L.fold_bytes, hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], pa.data(), pb, hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(d->host.l1[ph], rb, kFin * kPartials * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(d->host.l1[ph ^ 1], rb + kFin * kPartials, kFin * kPartials * sizeof(double),
-                     hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(d->host.step_dev, &sd, sizeof(sd), hipMemcpyHostToDevice));
+  int rc = put_partial_totals(d, ph ^ 1, t.part_tot);
+  if (rc) return rc;
+  for (int k = 0; k < 2; ++k) {
+    const int q = ph ^ k;
+    HIPCHECK(hipMemcpy(d->host.l1[q], t.l1[k], sizeof(t.l1[k]), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(d->host.macc[q], t.macc[k], sizeof(t.macc[k]), hipMemcpyHostToDevice));
+  }
+  HIPCHECK(fill_mhist(d, t.mhist[ph], t.mhist[ph ^ 1]));
+  HIPCHECK(hipMemcpy(d->host.step_dev, &t.step_dev, sizeof(t.step_dev), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemset(d->host.nf_flag, 0, sizeof(int)));
+  // the per-step records restart from the loaded state (the ring is not saved)
+  HIPCHECK(hipMemset(d->host.ring, 0xFF, kRing * sizeof(DiagRec)));
   d->inited = true;
+  return LBM_OK;
+}
+
+// Whether a step since the last initialisation or load met a non-finite
+// density or temperature (waits for the domain's stream).
+int lbm_nonfinite_seen(lbm_domain* d, int* seen) {
+  HIPCHECK(wait_batch(d));
+  int v = 0;
+  HIPCHECK(hipMemcpyAsync(&v, d->host.nf_flag, sizeof(int), hipMemcpyDeviceToHost, d->stream));
+  HIPCHECK(hipStreamSynchronize(d->stream));
+  *seen = v != 0;
   return LBM_OK;
 }
 
@@ -751,28 +850,27 @@ extern "C" int lbm_set_tile_rows(lbm_domain* d, int rows) {
   if (rows < 0) return lbm_fail(LBM_E_INVALID, "rows must be >= 0");
   // the batch holds copies of the domain's tiles
   if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch");
-  // The pending partial sums of the last launch are stored per tile: keep
-  // their totals in tile 0 of the new layout (the finalizers' slices of the
-  // new tiling then sum to the same values).
+  // State kept per tile moves to the new tiling: the pending partial sums of
+  // the last launch go to tile 0 as totals (the finalizers' slices of the
+  // new tiling then sum to the same values), and every new tile gets the
+  // common last reading of the running mass totals.
   const int ph = (int)(d->step & 1);
-  const size_t stride = d->host.pstride;
-  std::vector<double> part(stride * kPartials);
+  double tot[kPartials] = {0};
+  unsigned long long hist[2] = {0ull, 0ull};
   if (d->inited) {
     HIPCHECK(hipStreamSynchronize(d->stream));
-    HIPCHECK(hipMemcpy(part.data(), d->host.partials[ph ^ 1], part.size() * sizeof(double),
-                       hipMemcpyDeviceToHost));
+    int rc = partial_totals(d, ph ^ 1, tot);
+    if (rc) return rc;
+    HIPCHECK(hipMemcpy(&hist[0], d->host.mhist[0], sizeof(hist[0]), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(&hist[1], d->host.mhist[1], sizeof(hist[1]), hipMemcpyDeviceToHost));
   }
-  double tot[kPartials] = {0};
-  for (int q = 0; q < kPartials; ++q)
-    for (int t = 0; t < d->ntiles; ++t) tot[q] += part[(size_t)q * stride + t];
   d->rows = rows == 0 ? 0 : std::max(rows, kMinTileRows);
   int rc = lbm_build_tiles(d);
   if (rc) return rc;
   if (d->inited) {
-    std::fill(part.begin(), part.end(), 0.0);
-    for (int q = 0; q < kPartials; ++q) part[(size_t)q * stride] = tot[q];
-    HIPCHECK(hipMemcpy(d->host.partials[ph ^ 1], part.data(), part.size() * sizeof(double),
-                       hipMemcpyHostToDevice));
+    rc = put_partial_totals(d, ph ^ 1, tot);
+    if (rc) return rc;
+    HIPCHECK(fill_mhist(d, hist[0], hist[1]));
   }
   return LBM_OK;
 }

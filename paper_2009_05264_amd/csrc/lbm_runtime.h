@@ -32,6 +32,7 @@ struct lbm_domain {
   int rows = kDefaultTileRows;
   int grid = 0;  // 0: one workgroup per tile
   int simds = 1024;  // SIMDs of the device (automatic tile rows)
+  int device = 0;    // HIP device the domain was created on
   int batch_rows = 0;  // automatic rows chosen for the batch the domain is in (0: its own choice)
   float* psiw_d[2] = {nullptr, nullptr};
   float* Tw_d[2] = {nullptr, nullptr};
@@ -42,7 +43,7 @@ struct lbm_domain {
   bool inited = false;
   bool in_batch = false;
   hipStream_t batch_stream = nullptr;  // stream the domain's batch runs on (while in one)
-  std::vector<GraphEntry> graphs;  // replay graphs of this domain: [0] two steps, [1] 32 steps
+  std::vector<GraphEntry> graphs;  // replay graphs of this domain: [k] 2^k launch pairs
 };
 
 int lbm_fail(int code, const char* fmt, ...);
@@ -51,3 +52,7 @@ long long lbm_tile_count(int nx, int ny, int rows);  // tiles lbm_build_tiles ma
 int lbm_enqueue_steps(lbm_domain* d, int64_t n);
 int lbm_run_steps(lbm_domain* d, int64_t n);
 void lbm_drop_graphs(lbm_domain* d);
+int lbm_nonfinite_seen(lbm_domain* d, int* seen);
+// Replay graphs of a batch captured only when a call needs them (the serving
+// loop rebuilds its batch whenever the running set changes).
+void lbm_batch_lazy_graphs(lbm_batch* b);

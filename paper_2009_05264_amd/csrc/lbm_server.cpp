@@ -5,7 +5,10 @@
 // launches (one batch over their tile tables) -- until each reaches its step
 // budget.  Admission and retirement happen between quanta of steps, so a
 // request that arrives while others are on the device joins them at the
-// next quantum (continuous batching).
+// next quantum (continuous batching).  A request whose fields turn
+// non-finite is failed at the end of the quantum in which that happens and
+// its memory freed; the others go on unaffected (each domain keeps its own
+// state and reductions).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,6 +47,7 @@ struct Request {
   int64_t budget = 0, remaining = 0;
   size_t footprint = 0;
   int state = LBM_REQ_QUEUED;
+  int error = LBM_OK;  // why a request failed (LBM_E_NAN: fields turned non-finite)
   double t_submit = 0, t_start = 0, t_done = 0;
   lbm_domain* dom = nullptr;
 };
@@ -61,7 +65,7 @@ struct lbm_server {
   std::vector<uint64_t> active;   // admission order
   lbm_batch* batch = nullptr;
   size_t resident = 0, peak = 0;
-  int64_t done = 0;
+  int64_t done = 0, failed = 0;
   double lups = 0.0, busy = 0.0;
   uint64_t next_id = 1;
 };
@@ -200,8 +204,11 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
       for (uint64_t id : ids) {
         Request& r = s->reqs[id];
         s->queue.erase(std::find(s->queue.begin(), s->queue.end(), id));
-        if (start_request(s, r) != LBM_OK) {
+        const int src = start_request(s, r);
+        if (src != LBM_OK) {
           r.state = LBM_REQ_FAILED;  // e.g. the device allocation failed; lbm_last_error says why
+          r.error = src;
+          ++s->failed;
           continue;
         }
         s->resident += r.footprint;
@@ -222,6 +229,7 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
     for (uint64_t id : s->active) doms.push_back(s->reqs[id].dom);
     rc = lbm_batch_create(doms.data(), (int)doms.size(), nullptr, &s->batch);
     if (rc) return rc;
+    lbm_batch_lazy_graphs(s->batch);
   }
   int64_t q = s->quantum;
   double nodes = 0;
@@ -242,6 +250,17 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
   for (uint64_t id : s->active) {
     Request& r = s->reqs[id];
     r.remaining -= q;
+    int bad = 0;
+    rc = lbm_nonfinite_seen(r.dom, &bad);
+    if (rc) return rc;
+    if (bad) {
+      r.state = LBM_REQ_FAILED;
+      r.error = LBM_E_NAN;
+      r.t_done = t1;
+      ++s->failed;
+      retired = true;  // its domain is freed once the batch is dropped
+      continue;
+    }
     if (r.remaining == 0) {
       r.state = LBM_REQ_DONE;
       r.t_done = t1;
@@ -254,6 +273,10 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
   if (retired) {
     rc = drop_batch(s);  // releases the finished domains for read-out
     if (rc) return rc;
+    for (uint64_t id : s->active) {
+      Request& r = s->reqs[id];
+      if (r.state == LBM_REQ_FAILED) free_request(s, r);
+    }
   }
   s->active.swap(still);
   if (running) *running = (int)s->active.size();
@@ -265,6 +288,9 @@ extern "C" int lbm_server_poll(lbm_server* s, uint64_t id, int* state, double* t
   auto it = s->reqs.find(id);
   if (it == s->reqs.end()) return lbm_fail(LBM_E_INVALID, "unknown request %llu", (unsigned long long)id);
   *state = it->second.state;
+  if (it->second.state == LBM_REQ_FAILED)
+    lbm_fail(it->second.error, "request %llu failed (%s)", (unsigned long long)id,
+             it->second.error == LBM_E_NAN ? "its fields turned non-finite" : "it could not be started");
   if (time_to_solution_s)
     *time_to_solution_s = it->second.state == LBM_REQ_DONE ? it->second.t_done - it->second.t_submit : -1.0;
   return LBM_OK;
@@ -328,6 +354,7 @@ extern "C" int lbm_server_stats(lbm_server* s, lbm_server_info* out) {
   out->queued = (int64_t)s->queue.size();
   out->running = (int64_t)s->active.size();
   out->done = s->done;
+  out->failed = s->failed;
   out->resident_bytes = s->resident;
   out->peak_resident_bytes = s->peak;
   out->lups = s->lups;

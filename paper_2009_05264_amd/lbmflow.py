@@ -36,7 +36,7 @@ class Params(C.Structure):
         (n, C.c_double) for n in (
             "a", "b", "R", "omega", "beta", "c0", "g", "tau_f", "s_e", "s_eps", "s_q",
             "tau_g", "c_v", "ga_x", "ga_y", "fb_x", "fb_y", "u_in", "T_in", "U_out",
-            "T_iso", "rho_mid", "rho_ref", "T_ref", "rho_out")]
+            "T_iso", "rho_mid", "rho_ref", "T_ref", "rho_out", "G_wet")]
 
 
 class Diag(C.Structure):
@@ -57,7 +57,7 @@ class Request(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [("queued", C.c_int64), ("running", C.c_int64), ("done", C.c_int64),
                 ("resident_bytes", C.c_size_t), ("peak_resident_bytes", C.c_size_t),
-                ("lups", C.c_double), ("busy_seconds", C.c_double)]
+                ("lups", C.c_double), ("busy_seconds", C.c_double), ("failed", C.c_int64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -79,6 +79,7 @@ def lib():
         sig = {
             "lbm_last_error": (C.c_char_p, []),
             "lbm_params_default": (C.c_int, [C.POINTER(Params)]),
+            "lbm_neutral_G_wet": (C.c_double, [C.POINTER(Params)]),
             "lbm_required_bytes": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
             "lbm_create": (C.c_int, [C.POINTER(Params), vp, vp, C.c_size_t, C.POINTER(vp)]),
             "lbm_destroy": (C.c_int, [vp]),
@@ -135,12 +136,17 @@ def _dp(a):
 
 
 def default_params(**kw) -> Params:
+    """lbm_params_default with the given fields replaced; G_wet, when not
+    given (or None), is the library's neutral value for the final beta and g."""
     p = Params()
     _check(lib().lbm_params_default(C.byref(p)))
     for k, v in kw.items():
         if not hasattr(p, k):
             raise AttributeError(k)
-        setattr(p, k, v)
+        if v is not None:
+            setattr(p, k, v)
+    if kw.get("G_wet") is None:
+        p.G_wet = lib().lbm_neutral_G_wet(C.byref(p))
     return p
 
 

@@ -38,12 +38,25 @@ def test_binding_struct_sizes():
     from paper_2009_05264_amd import lbmflow as L
 
     txt = open(HEADER).read()
-    assert C.sizeof(L.Params) == 8 * 4 + 25 * 8
+    assert C.sizeof(L.Params) == 8 * 4 + 26 * 8
     assert C.sizeof(L.Diag) == 8 + 8 * 8
     assert "double rho_ref, T_ref;" in txt
-    # rho_out is the last member of lbm_params
+    # rho_out, then G_wet, close lbm_params
     assert txt.index("double rho_out;") > txt.index("double rho_ref, T_ref;")
-    assert txt.index("double rho_out;") < txt.index("} lbm_params;")
+    assert txt.index("double rho_out;") < txt.index("double G_wet;") < txt.index("} lbm_params;")
+    assert [f[0] for f in L.Params._fields_][-2:] == ["rho_out", "G_wet"]
+
+
+def test_default_G_wet_is_neutral(oracle_mod):
+    """The library's default adhesion strength (Eq. 15) equals the oracle's
+    neutral value, and follows beta and g when they change."""
+    from paper_2009_05264_amd import lbmflow as L
+
+    O = oracle_mod
+    assert L.default_params().G_wet == pytest.approx(O.Params().neutral_G_wet, rel=1e-15)
+    p = L.default_params(beta=1.3, g=-2.0)
+    assert p.G_wet == pytest.approx(O.Params(beta=1.3, g=-2.0).neutral_G_wet, rel=1e-15)
+    assert L.default_params(G_wet=-7.0).G_wet == -7.0
 
 
 def test_binding_names_match_header():
@@ -77,7 +90,7 @@ def test_server_structs_match_header():
     from paper_2009_05264_amd import lbmflow as L
 
     assert C.sizeof(L.Request) == 5 * 8 + 3 * 8 + 8
-    assert C.sizeof(L.ServerInfo) == 3 * 8 + 2 * 8 + 2 * 8
+    assert C.sizeof(L.ServerInfo) == 3 * 8 + 2 * 8 + 2 * 8 + 8
     txt = open(HEADER).read()
     for st in ("LBM_REQ_QUEUED = 0", "LBM_REQ_RUNNING = 1", "LBM_REQ_DONE = 2", "LBM_REQ_CANCELLED = 3",
                "LBM_REQ_FAILED = 4"):

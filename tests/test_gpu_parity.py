@@ -83,7 +83,12 @@ def run_pair(L, cfg, steps, storage=None, rows=None, init=None, **over):
 
 @pytest.mark.parametrize("storage", ["F32_DEV", "F32"])
 def test_channel_200x50_100_steps(L, storage):
-    """The 200x50 flow-boiling channel, 100 steps, FP32 compute."""
+    """The 200x50 flow-boiling channel, 100 steps, FP32 compute.  Parity
+    (1e-5) is claimed for FP32 deviation storage, the storage of every
+    benchmark and parity run.  Plain FP32 storage of the whole populations
+    rounds each f_i (up to ~2.9) to 24 bits every step; that rounding alone
+    puts u at ~2e-5 after 100 steps (measured 2.1e-5 on MI355X), so it is a
+    point of the precision study with the 5e-5 bound, not a parity case."""
     st = getattr(L, "STORE_" + storage)
     print(f"case: channel 200x50 storage={storage}", flush=True)
     d, o = run_pair(L, W.c1(), 100, storage=st)
@@ -226,6 +231,32 @@ def test_checkpoint_resume_bitwise(L, tmp_path):
     fa, fb = a.fields(), b.fields()
     for k in fa:
         assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_checkpoint_across_tilings(L, tmp_path):
+    """A checkpoint does not depend on the tiling: saved at 4 rows per tile,
+    loaded into a domain at 12 rows, the run continues bitwise like the
+    saved one (fields, diagnostics and the per-step records, whose pending
+    reductions and the buoyancy's mean cross the change)."""
+    cfg = W.c1()
+    a = make_gpu(L, cfg, rows=4)
+    a.init(**cfg.init_args())
+    a.step(37)
+    a.save(str(tmp_path / "ck.bin"))
+    a.step(25)
+    b = make_gpu(L, cfg, rows=12)
+    b.load(str(tmp_path / "ck.bin"))
+    b.step(25)
+    fa, fb = a.fields(), b.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    da, db = a.diag(), b.diag()
+    assert da == db
+    # records restart at the load: the 25 launches record states 35 to 59
+    # (state n is recorded during step n + 2)
+    ha, hb = a.diag_history()[-25:], b.diag_history()
+    assert [r["step"] for r in hb] == list(range(35, 60))
+    assert ha == hb
 
 
 def test_diag_history_records_every_step(L):
@@ -408,7 +439,9 @@ def test_autotuner_and_cache(L, tmp_path):
     b.close()
     lines = cache.read_text().split()
     assert len(lines) == 3 and lines[0].startswith("v2_n2_")
-    assert int(lines[1]) in (4, 6, 8, 12) and int(lines[2]) in (0, 8, 16)
+    # the autotuner's options (rows 4, 6, 7, 8, 12; grids 0, 8, 16 per CU),
+    # as documented at lbm_batch_create
+    assert int(lines[1]) in (4, 6, 7, 8, 12) and int(lines[2]) in (0, 8, 16)
     for c, d in zip(cfgs, doms):
         s = make_gpu(L, c)
         s.init(**c.init_args())

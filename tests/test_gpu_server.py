@@ -132,3 +132,39 @@ def test_cancel_and_cap(L):
         submit(L, srv, big, storage, 10)
     assert e.value.code == L.LBM_E_CAP
     srv.close()
+
+
+def test_non_finite_request_fails_alone(L):
+    """Failure isolation: among three ordinary requests, one whose buoyancy
+    (g_a = -1 in lattice units) drives its fields non-finite within a few
+    dozen steps is retired as failed (LBM_E_NAN) at the end of that quantum,
+    with its memory freed; the other three finish and equal their solo runs
+    bitwise."""
+    reqs = request_set()[:3]
+    bad = W.Channel(nx=67, ny=13, heater_len=5, seed=3, extra=dict(ga_y=-1.0))
+    srv = L.Server(1 << 34, max_slots=8, quantum=40)
+    print("case: server with one diverging request", flush=True)
+    ids = {submit(L, srv, *r): k for k, r in enumerate(reqs)}
+    bad_id = submit(L, srv, bad, "F32_DEV", 120)
+    results = {}
+    for _ in range(100):
+        running = srv.pump()
+        for rid, k in ids.items():
+            st, _ = srv.poll(rid)
+            assert st != L.REQ_FAILED, k
+            if st == L.REQ_DONE and k not in results:
+                cfg = reqs[k][0]
+                results[k] = srv.fields(rid, cfg.nx, cfg.ny)
+                srv.release(rid)
+        if running == 0 and srv.stats()["queued"] == 0:
+            break
+    st, t = srv.poll(bad_id)
+    assert st == L.REQ_FAILED and t == -1.0
+    assert "non-finite" in L.lib().lbm_last_error().decode()
+    info = srv.stats()
+    srv.close()
+    assert info["failed"] == 1 and info["done"] == 3 and info["resident_bytes"] == 0
+    for k, (cfg, storage, budget) in enumerate(reqs):
+        f_alone, _ = run_alone(L, cfg, storage, budget)
+        for key in f_alone:
+            assert np.array_equal(results[k][key], f_alone[key]), (k, key)

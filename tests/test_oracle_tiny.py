@@ -7,7 +7,7 @@ outlets, the wall closure of div u, the heater and pressure read-outs."""
 import numpy as np
 import pytest
 
-from tests.tiny_step import TinyLBM
+from tiny_step import TinyLBM
 
 CASES = {
     "periodic": dict(bc_x=0, bc_y=0),
