@@ -160,6 +160,22 @@ int lbm_set_wall_maps(lbm_domain* d, int side, const double* T_wall, const doubl
 int lbm_init_fields(lbm_domain* d, const double* rho0, const double* T0, double rho_uniform,
                     double T_uniform, double noise_rel, uint64_t seed);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops that re-initialise resident domains,
+ * harnesses that forbid hipMalloc): lbm_init_fields with the host arrays
+ * staged in a fixed device array of the library instead of hipMalloc'd
+ * memory.  Same arguments, same result (bitwise) and same synchronisation as
+ * lbm_init_fields; it calls no allocating routine.  With rho0 or T0 given,
+ * nx * ny must not exceed LBM_NOALLOC_MAX_NODES (LBM_E_INVALID otherwise;
+ * uniform initial states have no limit).  The staging array (16 MiB,
+ * 2 x LBM_NOALLOC_MAX_NODES doubles) is held by each GPU the library runs on
+ * until the process ends and is shared by every call on that GPU: calls
+ * that overlap on one GPU (from several host threads, or on several
+ * streams) race for it and must be serialised by the caller. */
+#define LBM_NOALLOC_MAX_NODES (1 << 20)
+int lbm_init_fields_noalloc(lbm_domain* d, const double* rho0, const double* T0, double rho_uniform,
+                            double T_uniform, double noise_rel, uint64_t seed);
+
 /* Enqueue nsteps time steps (the update of Sec. 2 summarised at the top of
  * this file) on the domain's stream (nsteps >= 0): one kernel launch per
  * step.  From 2 steps on they are replayed from captured hipGraphs of 2, 4,

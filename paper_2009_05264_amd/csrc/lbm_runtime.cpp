@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -526,6 +527,62 @@ extern "C" int lbm_init_fields(lbm_domain* d, const double* rho0, const double* 
   for (double* p : stage)
     if (p) (void)hipFree(p);
   return rc;
+}
+
+// ------------------------------------------------------------------ init without allocation
+// lbm_init_fields_noalloc stages the host arrays in this fixed device array
+// instead of hipMalloc'd memory: two planes (density, temperature) of at
+// most LBM_NOALLOC_MAX_NODES doubles, held by every device the library runs
+// on until the process ends.  In host code `scratch` only names the symbol;
+// its device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[2 * LBM_NOALLOC_MAX_NODES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (looked up on the first call on
+// that device, with it current).
+int scratch_on(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return lbm_fail(LBM_E_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIPCHECK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHECK(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPCHECK(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      return lbm_fail(LBM_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" int lbm_init_fields_noalloc(lbm_domain* d, const double* rho0, const double* T0, double rho_u,
+                                       double T_u, double noise, uint64_t seed) {
+  double sum = 0.0;
+  int rc = init_args(d, rho0, T0, rho_u, T_u, noise, seed, &sum);
+  if (rc) return rc;
+  const size_t n = (size_t)d->P.nx * d->P.ny;
+  if ((rho0 || T0) && n > (size_t)LBM_NOALLOC_MAX_NODES)
+    return lbm_fail(LBM_E_INVALID, "%d x %d = %zu nodes exceed the %d of the fixed staging array; use lbm_init_fields",
+                    d->P.nx, d->P.ny, n, LBM_NOALLOC_MAX_NODES);
+  double* base = nullptr;
+  rc = scratch_on(d->device, &base);
+  if (rc) return rc;
+  double* stage[2] = {nullptr, nullptr};
+  const double* src[2] = {rho0, T0};
+  for (int k = 0; k < 2; ++k) {
+    if (!src[k]) continue;
+    stage[k] = base + (size_t)k * LBM_NOALLOC_MAX_NODES;
+    HIPCHECK(hipMemcpyAsync(stage[k], src[k], n * sizeof(double), hipMemcpyHostToDevice, d->stream));
+  }
+  return init_on_device(d, stage[0], stage[1], rho_u, T_u, noise, seed, sum);
 }
 
 int lbm_enqueue_steps(lbm_domain* d, int64_t nsteps) {

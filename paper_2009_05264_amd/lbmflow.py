@@ -22,6 +22,7 @@ STORE_F32, STORE_F32_DEV, STORE_F16_DEV, STORE_BF16_DEV = 0, 1, 2, 3
 BCX_PERIODIC, BCX_CHANNEL, BCX_CHANNEL_P = 0, 1, 2
 BCY_PERIODIC, BCY_WALLS = 0, 1
 SIDE_S, SIDE_N = 0, 1
+NOALLOC_MAX_NODES = 1 << 20  # LBM_NOALLOC_MAX_NODES
 
 
 class LbmError(RuntimeError):
@@ -85,6 +86,7 @@ def lib():
             "lbm_destroy": (C.c_int, [vp]),
             "lbm_set_wall_maps": (C.c_int, [vp, C.c_int, dp, dp, C.POINTER(C.c_int32)]),
             "lbm_init_fields": (C.c_int, [vp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_uint64]),
+            "lbm_init_fields_noalloc": (C.c_int, [vp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_uint64]),
             "lbm_step": (C.c_int, [vp, C.c_int64]),
             "lbm_sync": (C.c_int, [vp]),
             "lbm_step_count": (C.c_int64, [vp]),
