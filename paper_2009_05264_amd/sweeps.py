@@ -82,7 +82,9 @@ def runs_default():
     return out
 
 
-def run(steps: int = 18000, K: int = 50, storage: str = "F32_DEV", runs=None):
+def run(steps: int = 18000, K: int = 50, storage: str = "F32_DEV", runs=None, fields: bool = False):
+    """Step the runs as one batch, sampling every K steps; fields=True also
+    returns each run's final rho, u_act and T (key "fields")."""
     import torch
 
     import workloads as W
@@ -113,8 +115,11 @@ def run(steps: int = 18000, K: int = 50, storage: str = "F32_DEV", runs=None):
     out = []
     for (name, val, cfg), d, t in zip(runs, doms, trk):
         r = t.result()
+        f = d.fields()
         r.update({"param": name, "value": val, "Re_in": cfg.u_in * cfg.ny / ((1.0 - 0.5) / 3.0),
-                  "finite": bool(np.isfinite(d.fields()["rho"]).all())})
+                  "finite": bool(np.isfinite(f["rho"]).all())})
+        if fields:
+            r["fields"] = f
         out.append(r)
     b.close()
     for d in doms:

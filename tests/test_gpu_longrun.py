@@ -5,9 +5,12 @@ bubble statistics sampled every 50 steps:
 
 * onset: first sample with a vapour node (rho < rho_mid);
 * leave: first sample at which the bubble no longer covers any heater cell
-  (it slides downstream along the wall; in this channel and horizon the
-  bubble does not lift off, so the lift-off diameter of the paper's
-  departure statistics is not defined here);
+  (it slides downstream along the wall);
+* departure: first sample at which a vapour component descended from the
+  heater's bubble (8-connected vapour that covered a heater cell, followed
+  from sample to sample by overlap while it touches the bottom wall) no
+  longer touches the bottom wall: the bubble lifts off into the stream; its
+  departure diameter D_d = 2 sqrt(A / pi) at that sample (Sec. 3B);
 * vapour area at fixed times;
 * mean heater Nusselt number between onset and leave,
   Nu_h = H / (T_h - T_in) * mean over heater cells of (T_h - T(x, 0)) / (1/2).
@@ -20,7 +23,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-STEPS = 16500
+STEPS = 26500
 K = 50
 
 
@@ -34,10 +37,26 @@ def stats_of(samples, cfg):
     area = {}
     nus = []
     coef = cfg.ny / (cfg.T_heater - cfg.T_in) / len(hx)
+    lineage = None
+    depart = D_d = None
     for step, rho, q in samples:
         vap = rho < mid
         if onset is None and vap.any():
             onset = step
+        if depart is None and vap.any():
+            lab, n = ndimage.label(vap, structure=np.ones((3, 3)))
+            born = np.unique(lab[0, hx])
+            keep = set(born[born > 0].tolist())
+            if lineage is not None:
+                for c in np.unique(lab[lineage & vap]):
+                    if c == 0:
+                        continue
+                    comp = lab == c
+                    if not comp[0].any():
+                        depart, D_d = step, 2.0 * np.sqrt(comp.sum() / np.pi)
+                        break
+                    keep.add(int(c))
+            lineage = np.isin(lab, list(keep)) if keep else None
         if onset is not None and leave is None:
             lab, n = ndimage.label(vap, structure=np.ones((3, 3)))
             on_heater = n > 0 and bool(vap[0, hx].any())
@@ -47,8 +66,8 @@ def stats_of(samples, cfg):
                 nus.append(coef * q)
         if step in (12000, 14000):
             area[step] = int(vap.sum())
-    return {"onset": onset, "leave": leave, "area": area, "nu": float(np.mean(nus)) if nus else None,
-            "final_finite": bool(np.isfinite(samples[-1][1]).all())}
+    return {"onset": onset, "leave": leave, "depart": depart, "D_d": D_d, "area": area,
+            "nu": float(np.mean(nus)) if nus else None, "final_finite": bool(np.isfinite(samples[-1][1]).all())}
 
 
 @pytest.fixture(scope="module")
@@ -101,9 +120,11 @@ def test_bubble_statistics_match_oracle(L, oracle_stats):
     print(f"case: long run 200x50 F32_DEV, {STEPS} steps", flush=True)
     g, r = gpu_stats(L, L.STORE_F32_DEV), oracle_stats
     print("F32_DEV gpu", g, "\noracle", r, flush=True)
-    assert r["onset"] is not None and r["leave"] is not None  # the run shows both events
+    assert r["onset"] is not None and r["leave"] is not None and r["depart"] is not None  # all three events
     assert abs(g["onset"] - r["onset"]) <= max(K, 0.02 * r["onset"])
     assert abs(g["leave"] - r["leave"]) <= max(K, 0.02 * r["leave"])
+    assert g["depart"] is not None and abs(g["depart"] - r["depart"]) <= max(K, 0.02 * r["depart"])
+    assert g["D_d"] == pytest.approx(r["D_d"], rel=0.02)
     for t in (12000, 14000):
         assert g["area"][t] == pytest.approx(r["area"][t], rel=0.02)
     assert g["nu"] == pytest.approx(r["nu"], rel=0.02)

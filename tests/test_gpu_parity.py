@@ -123,19 +123,31 @@ def test_channel_diagnostics(L):
     (61, 70, 2, 0),    # pressure exit, periodic in y
 ])
 def test_shapes_and_boundaries(L, nx, ny, bcx, bcy):
-    """Ragged tiles and every boundary combination, 40 steps, with a liquid
-    blob so that interfaces cross tile edges."""
+    """Ragged tiles and every boundary combination, 100 steps, with a vapour
+    bubble (tanh interface) so that interfaces cross tile edges; 1e-5 on rho
+    and T everywhere, and on u except in three cases whose velocity error is
+    set by the FP32 resolution of the interface forces against a small or
+    transient velocity scale (measured on MI355X):
+      * 7x5, periodic: the fluid is nearly at rest (max |u| ~1.2e-3); the
+        absolute error ~5e-8 is 6e-5 of that -> 1e-4;
+      * 67x13 between walls: a radius-4 bubble filling a third of the gap,
+        max |u| ~0.014; absolute error ~1.4e-7, 1.0e-5 -> 2e-5;
+      * 61x70 channel periodic in y (either exit): the bubble's initial
+        adjustment drives max |u| to ~0.13 within 20 steps, where the
+        absolute error of ~1.5e-6 is set and then stays; 1.3e-5 -> 2e-5."""
     print(f"case: {nx}x{ny} bc=({bcx},{bcy})", flush=True)
     cfg = W.Channel(nx=nx, ny=ny, heater_len=max(1, nx // 5))
     y, x = np.mgrid[0:ny, 0:nx]
-    r0 = np.where((x - nx / 3) ** 2 + (y - ny / 2) ** 2 < (min(nx, ny) / 3) ** 2, W.RHO_V, W.RHO_L)
+    rad = np.sqrt((x - nx / 3) ** 2 + (y - ny / 2) ** 2)
+    r0 = W.RHO_V + (W.RHO_L - W.RHO_V) * 0.5 * (1 + np.tanh((rad - min(nx, ny) / 3) / 2.0))
     r0 = r0 * (1 + 1e-3 * np.sin(x + 2 * y))
     init = dict(rho0=r0, T_u=cfg.T_sat)
     extra = dict(rho_out=W.RHO_L) if bcx == 2 else {}
-    d, o = run_pair(L, cfg, 40, init=init, bc_x=bcx, bc_y=bcy, rows=8, **extra)
+    d, o = run_pair(L, cfg, 100, init=init, bc_x=bcx, bc_y=bcy, rows=8, **extra)
     e = rel_errors(d.fields(), o.fields())
     print(e)
-    assert e["rho"] < 2e-5 and e["T"] < 2e-5 and e["u"] < 5e-5, e
+    tol_u = {(7, 5): 1e-4, (67, 13): 2e-5, (61, 70): 2e-5}.get((nx, ny), TOL)
+    assert e["rho"] < TOL and e["T"] < TOL and e["u"] < tol_u, e
 
 
 @pytest.mark.parametrize("rho_out_frac", [1.0, 0.97])
@@ -325,6 +337,31 @@ def test_batch_equals_solo(L):
         assert dr["step"] == dd["step"] and dr["mass"] == dd["mass"] and dr["vapor_cells"] == dd["vapor_cells"]
 
 
+def test_batch_member_matches_oracle(L):
+    """A domain stepped inside a batch of uneven domains (as the ensemble and
+    the serving loop run them) against the oracle: the middle member of
+    three, 100 steps from an odd start, 1e-5."""
+    cfgs = [W.Channel(nx=130, ny=30, heater_len=10, seed=5), W.Channel(nx=250, ny=41, heater_len=16, seed=6),
+            W.Channel(nx=64, ny=64, heater_len=20, seed=7)]
+    print("case: batch member 250x41 vs oracle, 101 steps", flush=True)
+    doms = []
+    for c in cfgs:
+        d = make_gpu(L, c)
+        d.init(**c.init_args())
+        d.step(1)
+        doms.append(d)
+    b = L.Batch(doms)
+    b.step(100)
+    b.sync()
+    b.close()
+    o = make_oracle(cfgs[1])
+    o.init(**cfgs[1].init_args())
+    o.step(101)
+    e = rel_errors(doms[1].fields(), o.fields())
+    print(e)
+    assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
+
+
 def test_channel_1600x200_parity(L):
     """Full single-instance size, 100 steps (the same launch configuration as
     the benchmark), compared on every node."""
@@ -411,6 +448,49 @@ def test_pressure_exit_paper_cross_section_long_run(L):
     e = rel_errors(g, r)
     print(e, flush=True)
     assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
+
+
+def test_heated_paper_channel(L):
+    """The paper's channel (Sec. 2C): 40 x 1000, constant-pressure exit at
+    rho_l, T_in = T_sat = 0.9 Tc, Re_in = 0.96, 10 000 unheated steps, then a
+    5-node heater at L/5 switched on at 1.2 Tc through the wall maps, 3000
+    heated steps: GPU against the oracle at 1e-5 on every node (the heated
+    spot on the wall -- a near-critical low-density region of ~11 nodes --
+    forms in this window)."""
+    from oracle import oracle as O
+
+    Tc = W.TC
+    Tin = 0.9 * Tc
+    rl, rv, _ = O.maxwell(Tin)
+    nx, ny = 1000, 40
+    kw = dict(nx=nx, ny=ny, bc_x=2, bc_y=1, rho_out=rl, u_in=0.96 / 6.0 / ny, T_in=Tin, T_iso=Tin,
+              rho_mid=0.5 * (rl + rv), ga_y=-5e-5, tau_f=1.0, tau_g=0.6, c_v=6.0, omega=0.344)
+    rw = rv + 0.6 * (rl - rv)
+    heater = np.zeros(nx, np.int32)
+    heater[nx // 5 - 2: nx // 5 + 3] = 1
+    print("case: paper channel 40x1000, 10000 + 3000 heated steps", flush=True)
+    d = L.Domain(L.default_params(storage=L.STORE_F32_DEV, rho_ref=rl, T_ref=Tin, **kw))
+    o = O.Oracle(O.Params(**kw))
+    for side in (0, 1):
+        d.set_wall(side, np.full(nx, Tin), np.full(nx, rw))
+        o.set_wall(side, np.full(nx, Tin), np.full(nx, rw))
+    ia = dict(rho_u=rl, T_u=Tin, noise=1e-3, seed=11)
+    d.init(**ia)
+    o.init(**ia)
+    d.step(10000)
+    o.step(10000)
+    Th = np.where(heater == 1, 1.2 * Tc, Tin)
+    d.set_wall(L.SIDE_S, Th, np.full(nx, rw), heater)
+    o.set_wall(0, Th, np.full(nx, rw), heater)
+    d.step(3000)
+    o.step(3000)
+    g, r = d.fields(), o.fields()
+    assert np.isfinite(g["rho"]).all() and r["rho"].min() < 3.0  # the heated spot is there
+    e = rel_errors(g, r)
+    print(e, flush=True)
+    assert e["rho"] < TOL and e["T"] < TOL and e["u"] < TOL, e
+    gd, od = d.diag(), o.diag()
+    assert gd["heater_q"] == pytest.approx(od["heater_q"], rel=1e-4)
 
 
 def test_autotuner_and_cache(L, tmp_path):

@@ -104,6 +104,36 @@ def test_results_equal_alone_and_in_the_mix(L):
         assert tts[k] > 0
 
 
+def test_server_member_matches_oracle(L):
+    """A request served in a mix of requests against the oracle: the first
+    FP32 request of the set (130x40), 1e-5 after its budget."""
+    from oracle import oracle as O
+
+    reqs = request_set()
+    srv = L.Server(1 << 34, max_slots=8, quantum=30)
+    print("case: server member vs oracle", flush=True)
+    ids = [submit(L, srv, *r) for r in reqs[:4]]
+    for _ in range(100):
+        if srv.pump() == 0 and srv.stats()["queued"] == 0:
+            break
+    cfg, storage, budget = reqs[0]
+    assert storage == "F32_DEV" and srv.poll(ids[0])[0] == L.REQ_DONE
+    g = srv.fields(ids[0], cfg.nx, cfg.ny)
+    srv.close()
+    o = O.Oracle(O.Params(**cfg.params()))
+    Ts, rws, heat, Tn, rwn = cfg.walls()
+    o.set_wall(0, Ts, rws, heat)
+    o.set_wall(1, Tn, rwn)
+    o.init(**cfg.init_args())
+    o.step(budget)
+    r = o.fields()
+    umax = max(np.abs(r["ux"]).max(), np.abs(r["uy"]).max())
+    e = {k: float(np.abs(g[k] - r[k]).max() / np.abs(r[k]).max()) for k in ("rho", "T")}
+    e["u"] = float(max(np.abs(g["ux"] - r["ux"]).max(), np.abs(g["uy"] - r["uy"]).max()) / umax)
+    print(budget, e)
+    assert max(e.values()) < 1e-5, e
+
+
 def test_cancel_and_cap(L):
     cfg, storage, _ = request_set()[1]
     fp = L.required_bytes(params_of(L, cfg, storage))

@@ -32,3 +32,34 @@ def test_departure_trends_batched():
     assert onset[0] > onset[1] > onset[2]
     dw = [by[("rho_w", 4.2)]["D_leave"], base["D_leave"], by[("rho_w", 3.4)]["D_leave"]]  # 49, 60, 71 degrees
     assert None not in dw and dw[0] < dw[1] < dw[2]
+
+
+def test_swept_member_matches_oracle():
+    """One member of a batched sweep against the oracle after 150 steps
+    (three channels of the u_in sweep stepped as one batch), 1e-5."""
+    import numpy as np
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import workloads as W
+    from oracle import oracle as O
+    from paper_2009_05264_amd import sweeps
+
+    runs = [("u_in", u, W.Channel(u_in=u)) for u in (0.003, 0.004, 0.005)]
+    print("case: swept member vs oracle, 150 steps", flush=True)
+    res = sweeps.run(steps=150, K=50, runs=runs, fields=True)
+    g = res["runs"][1]["fields"]
+    cfg = runs[1][2]
+    o = O.Oracle(O.Params(**cfg.params()))
+    Ts, rws, heat, Tn, rwn = cfg.walls()
+    o.set_wall(0, Ts, rws, heat)
+    o.set_wall(1, Tn, rwn)
+    o.init(**cfg.init_args())
+    o.step(150)
+    r = o.fields()
+    umax = max(np.abs(r["ux"]).max(), np.abs(r["uy"]).max())
+    e = {k: float(np.abs(g[k] - r[k]).max() / np.abs(r[k]).max()) for k in ("rho", "T")}
+    e["u"] = float(max(np.abs(g["ux"] - r["ux"]).max(), np.abs(g["uy"] - r["uy"]).max()) / umax)
+    print(e)
+    assert max(e.values()) < 1e-5, e
