@@ -76,6 +76,9 @@ def test_workload_constants_match_oracle(oracle_mod):
     rl, rv, _ = O.maxwell(W.TSAT_FRAC * W.TC, omega=0.344)
     assert W.RHO_L == pytest.approx(rl, rel=1e-9)
     assert W.RHO_V == pytest.approx(rv, rel=1e-9)
+    rl, rv, _ = O.maxwell(0.9 * W.TC, omega=0.32)
+    assert W.RHO_L_POOL == pytest.approx(rl, rel=1e-9)
+    assert W.RHO_V_POOL == pytest.approx(rv, rel=1e-9)
 
 
 def test_ensemble_is_seeded():

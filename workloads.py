@@ -5,7 +5,9 @@ the method's arithmetic.  The numeric constants are inputs:
   * TC: critical temperature of the Peng-Robinson constants a = 2/49,
     b = 2/21, R = 1 (pinned against the oracle's EOS in the CPU tests);
   * RHO_L, RHO_V: Maxwell coexistence densities at 0.86 Tc, omega = 0.344
-    (pinned against the oracle's Maxwell construction);
+    (pinned against the oracle's Maxwell construction); RHO_L_POOL,
+    RHO_V_POOL the same at 0.9 Tc with omega = 0.32 (R134a), the state of
+    the pool-boiling validation;
   * RHO_W_60: false wall density giving a ~60 degree contact angle at
     0.86 Tc (from the oracle's sessile-drop sweep, tests/golden/contact_angle_0p86Tc.json);
     wall_density_for_angle() reads that stored table backwards for any angle
@@ -28,6 +30,8 @@ TSAT_FRAC = 0.86
 RHO_L = 6.4989457632878835
 RHO_V = 0.3796789993997205
 RHO_W_60 = 3.8
+RHO_L_POOL = 5.881229445687165
+RHO_V_POOL = 0.5901822861200811
 
 
 @dataclass
@@ -136,6 +140,52 @@ def _partial_wetting_range():
 
 
 MIN_PARTIAL_ANGLE, MAX_PARTIAL_ANGLE = _partial_wetting_range()
+
+
+@dataclass
+class Pool:
+    """Pool-boiling box (Sec. 2D): saturated R134a at 0.9 Tc (omega 0.32),
+    periodic sides, the bottom wall at T_sat with a heater of heater_len
+    cells at its centre, a liquid pool of depth `depth` under a vapour layer
+    (the free surface) capped by a non-wetting wall (false density rho_v),
+    buoyancy g_a downwards.  The box is 4 times wider than tall."""
+    nx: int = 512
+    ny: int = 128
+    depth: int = 112
+    ga: float = 5e-5
+    T_heater_over_Tc: float = 1.2
+    heater_len: int = 11
+    rho_w: float = 3.5          # false wall density of the bottom wall
+    rho_w_heater: float = 1.2   # and of the heater cells
+    tau_g: float = 0.6
+    c_v: float = 6.0
+
+    @property
+    def T_sat(self):
+        return 0.9 * TC
+
+    def params(self) -> dict:
+        return dict(nx=self.nx, ny=self.ny, bc_x=0, bc_y=1, u_in=0.0, T_in=self.T_sat, T_iso=self.T_sat,
+                    rho_mid=0.5 * (RHO_L_POOL + RHO_V_POOL), ga_x=0.0, ga_y=-self.ga, tau_f=1.0,
+                    tau_g=self.tau_g, c_v=self.c_v, omega=0.32)
+
+    def heater(self) -> np.ndarray:
+        h = np.zeros(self.nx, np.int32)
+        c = self.nx // 2 - self.heater_len // 2
+        h[c: c + self.heater_len] = 1
+        return h
+
+    def walls(self):
+        """(T_south, rho_w_south, heater, T_north, rho_w_north), each [nx]."""
+        h = self.heater()
+        Ts = np.where(h == 1, self.T_heater_over_Tc * TC, self.T_sat)
+        rws = np.where(h == 1, self.rho_w_heater, self.rho_w)
+        return Ts, rws, h, np.full(self.nx, self.T_sat), np.full(self.nx, RHO_V_POOL)
+
+    def init_args(self) -> dict:
+        y = np.arange(self.ny)[:, None] * np.ones((1, self.nx))
+        rho0 = RHO_V_POOL + (RHO_L_POOL - RHO_V_POOL) * 0.5 * (1 - np.tanh((y - self.depth) / 2.0))
+        return dict(rho0=rho0, T_u=self.T_sat)
 
 
 def roofline_channel() -> Channel:
