@@ -63,3 +63,23 @@ def test_swept_member_matches_oracle():
     e["u"] = float(max(np.abs(g["ux"] - r["ux"]).max(), np.abs(g["uy"] - r["uy"]).max()) / umax)
     print(e)
     assert max(e.values()) < 1e-5, e
+
+
+def test_regime_map_slug_at_low_reynolds():
+    """The regime map of the paper's channel from one batched ensemble
+    (Re_in x heater temperature, 10 000 unheated + 15 000 heated steps): at
+    Re_in = 0.48 the vapour grows into a slug spanning the channel height,
+    at Re_in = 1.92 it stays an attached bubble (Sec. 3C reports the slug
+    regime at the lowest Reynolds number)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_05264_amd import regimes
+
+    print("case: regime map, 4 channels 40x1000, 25000 steps", flush=True)
+    res = regimes.run(Res=(0.48, 1.92), Ths=(1.2, 1.4), heated=15000)
+    reg = {(r["Re_in"], r["T_heater_over_Tc"]): r for r in res["runs"]}
+    print(res["runs"], flush=True)
+    assert reg[(0.48, 1.4)]["regime"] == "slug"
+    assert all(reg[(1.92, t)]["regime"] == "attached bubble" for t in (1.2, 1.4))
