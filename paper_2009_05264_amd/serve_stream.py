@@ -3,13 +3,16 @@ library's continuous-batching server (lbm_server_*), in real time.
 
 Requests are drawn like the batched ensemble (Lx in {400, 800, 1200, 1600},
 Ly in {50, 100, 200}, u_in ~ U[0.002, 0.01], superheat ~ U[0.05, 0.2],
-wall density ~ U[3.0, 4.6]) with step budgets ~ U{lo..hi}, FP16-deviation
+contact angle ~ U[30, 120] degrees through the wall-density calibration
+table) with step budgets ~ U{lo..hi}, FP16-deviation
 storage with probability p16, and arrive with exponential gaps (seeded).
 The host loop submits every request whose arrival time has passed, then runs
 one server quantum; a request that arrives while others are on the device
 joins them at the next quantum.  Reports aggregate MLUPS (lattice updates /
-makespan), p50/p99 time to solution, and optionally checks sampled requests
-against the same solve run alone.
+makespan), p50/p99 time to solution of the completed requests, the requests
+the server failed (fields turned non-finite; they are retired and freed
+while the others go on), and optionally checks sampled requests against the
+same solve run alone.
 
     python3 paper_2009_05264_amd/serve_stream.py --requests 256 --rate 4
 """
@@ -38,8 +41,9 @@ def draw_stream(n, rate, lo, hi, p16, seed):
         nx = int(rng.choice([400, 800, 1200, 1600]))
         ny = int(rng.choice([50, 100, 200]))
         cfg = W.Channel(nx=nx, ny=ny, u_in=float(rng.uniform(0.002, 0.01)),
-                        superheat=float(rng.uniform(0.05, 0.2)), heater_len=int(0.4 * ny),
-                        rho_w=float(rng.uniform(3.0, 4.6)), seed=5000 + i)
+                        superheat=float(rng.uniform(0.05, 0.2)), heater_len=int(0.4 * ny), seed=5000 + i)
+        cfg.theta = float(rng.uniform(30.0, 120.0))
+        cfg.rho_w = W.wall_density_for_angle(max(cfg.theta, W.MIN_PARTIAL_ANGLE))
         storage = "F16_DEV" if rng.uniform() < p16 else "F32_DEV"
         budget = int(rng.integers(lo, hi + 1))
         out.append((float(t[i]), cfg, storage, budget))
@@ -61,6 +65,7 @@ def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0,
     ids, tts = {}, {}
     check_set = set(np.random.default_rng(seed + 1).choice(n, size=min(check, n), replace=False).tolist())
     kept = {}
+    failed = {}
     nxt = 0
     t0 = time.perf_counter()
     last_report = 0.0
@@ -80,7 +85,11 @@ def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0,
         for rid, k in list(ids.items()):
             st, t = srv.poll(rid)
             if st == L.REQ_FAILED:
-                raise RuntimeError(f"request {k} failed: {L.lib().lbm_last_error().decode()}")
+                # its fields turned non-finite (the server freed it; the others go on)
+                failed[k] = L.lib().lbm_last_error().decode()
+                tts[k] = None
+                del ids[rid]
+                continue
             if st == L.REQ_DONE:
                 tts[k] = t
                 if k in check_set:
@@ -93,14 +102,15 @@ def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0,
     makespan = time.perf_counter() - t0
     info = srv.stats()
     srv.close()
-    lups = sum(c.nx * c.ny * b for _, c, _, b in reqs)
-    t = np.array([tts[k] for k in range(n)])
+    lups = info["lups"]  # lattice updates the device did (failed requests up to their failure)
+    t = np.array([tts[k] for k in range(n) if tts[k] is not None])
     out = {"requests": n, "rate_per_s": rate, "budget_range": [lo, hi], "p_fp16": p16, "seed": seed,
            "cap_GB": cap_gb, "quantum_steps": quantum,
            "aggregate_MLUPS": round(lups / makespan / 1e6, 1), "makespan_s": round(makespan, 2),
            "device_busy_s": round(info["busy_seconds"], 2),
            "tts_p50_s": round(float(np.percentile(t, 50)), 3), "tts_p99_s": round(float(np.percentile(t, 99)), 3),
-           "peak_resident_GB": round(info["peak_resident_bytes"] / 1e9, 3)}
+           "peak_resident_GB": round(info["peak_resident_bytes"] / 1e9, 3),
+           "failed_nonfinite": sorted(failed), "completed": int(len(t))}
     if check:
         bad = []
         for k, rho_mix in kept.items():
