@@ -17,6 +17,14 @@
  *
  * Where the paper is silent, ambiguous or garbled, the reading taken is
  * stated in a comment at the point where it shapes the code.
+ *
+ * Parity unpinned: no closed form, invariant or printed value fixes the
+ * following, which are checked only against the GPU path and, for the
+ * boundary rules, against a second implementation written separately: the
+ * convective outlet beyond its uniform-stream steady state; the values of
+ * c_v and tau_g themselves (the form of the phase-change source is pinned);
+ * absolute contact angles; long-run bubble statistics against the paper's
+ * printed times.
  */
 #include <math.h>
 #include <omp.h>
