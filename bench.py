@@ -23,8 +23,9 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & HBM GB/s (coupled D2Q9+T step); batched MLUPS, p50/p99 solve time"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {0: 144, 1: 144, 2: 72, 3: 72}  # 18 values read + 18 written, once each
-# the step kernel and the host code that shapes its tiles
-KERNEL_SRC = [os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_kernels.hip"), os.path.join(ROOT, "paper_2009_05264_amd", "csrc", "lbm_tiles.cpp")]
+# the step kernel, the host code that shapes its tiles, and the header with
+# the store-policy threshold: what the measured traffic depends on
+KERNEL_SRC = [os.path.join(ROOT, "paper_2009_05264_amd", "csrc", f) for f in ("lbm_kernels.hip", "lbm_tiles.cpp", "lbm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
 
 

@@ -106,7 +106,8 @@ static int replay_steps(hipStream_t s, std::vector<GraphEntry>& g, int64_t n, bo
 
 static int enqueue_domain_phase(void* ctx, int phase) {
   lbm_domain* d = (lbm_domain*)ctx;
-  HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->fins_d, kFin, d->grid, phase, d->stream));
+  HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->fins_d, kFin, d->grid, phase,
+                           d->write_through, d->stream));
   return LBM_OK;
 }
 
@@ -139,6 +140,7 @@ struct lbm_batch {
     int grid = 0;
     FinEntry* fins_d = nullptr;  // finalizer waves of the group's domains
     int nfins = 0;
+    bool write_through = false;  // the group's A/B state is at most kWriteThroughMaxBytes
   };
   std::vector<Group> groups;
   std::vector<GraphEntry> graphs;  // [k]: 2^k launch pairs
@@ -159,7 +161,9 @@ static int build_groups(lbm_batch* b) {
   b->groups.clear();
   std::map<int, std::vector<Tile>> by;
   std::map<int, std::vector<FinEntry>> fby;
+  std::map<int, size_t> state_by;
   for (lbm_domain* d : b->doms) {
+    state_by[d->P.storage] += d->state_ab;
     auto& v = by[d->P.storage];
     v.insert(v.end(), d->tiles_h.begin(), d->tiles_h.end());
     for (int f = 0; f < kFin; ++f) fby[d->P.storage].push_back(FinEntry{d->dev, f, 0});
@@ -170,6 +174,7 @@ static int build_groups(lbm_batch* b) {
     g.ntiles = (int)kv.second.size();
     const auto& fl = fby[kv.first];
     g.nfins = (int)fl.size();
+    g.write_through = state_by[kv.first] <= kWriteThroughMaxBytes;
     HIPCHECK(hipMalloc(&g.tiles_d, g.ntiles * sizeof(Tile)));
     HIPCHECK(hipMemcpy(g.tiles_d, kv.second.data(), g.ntiles * sizeof(Tile), hipMemcpyHostToDevice));
     HIPCHECK(hipMalloc(&g.fins_d, g.nfins * sizeof(FinEntry)));
@@ -182,7 +187,8 @@ static int build_groups(lbm_batch* b) {
 static int enqueue_batch_phase(void* ctx, int phase) {
   lbm_batch* b = (lbm_batch*)ctx;
   for (auto& g : b->groups)
-    HIPCHECK(lbm_launch_step(g.storage, g.tiles_d, g.ntiles, g.fins_d, g.nfins, g.grid, phase, b->stream));
+    HIPCHECK(lbm_launch_step(g.storage, g.tiles_d, g.ntiles, g.fins_d, g.nfins, g.grid, phase, g.write_through,
+                             b->stream));
   return LBM_OK;
 }
 

@@ -90,6 +90,10 @@ typedef const DevDomain AS4& DRef;
 // wave-uniform byte offset per distribution plane (SGPR) and one per-lane
 // byte offset per row (VGPR).
 typedef __amdgpu_buffer_rsrc_t Rsrc;
+// Cache-policy operand of the state stores: 0 (default, write-back in the L2)
+// or kWriteThrough (SC1: agent-scope stores, which the L2 writes through);
+// the host picks one per launch from the size of the state it touches.
+constexpr int kWriteThrough = 16;
 // Byte offsets at or above kRange are outside the resource: stores there are
 // dropped and loads return 0 (raw-buffer bounds check), which lets lanes
 // without a node of their own issue the same store instruction unmasked.
@@ -108,8 +112,9 @@ struct BufIO<LBM_STORE_F32> {
   static __device__ __forceinline__ float ld(Rsrc r, int voff, int soff) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff + IMM * 4, soff, 0));
   }
+  template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, CP);
   }
 };
 template <>
@@ -138,6 +143,7 @@ struct PairIO<LBM_STORE_F32> {
     g = __uint_as_float((uint32_t)(w >> 32));
   }
   typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
     // Empty register constraint: keeps the pair operands as register values,
     // so that the packing below is not rewritten into a widened memory load
@@ -145,7 +151,7 @@ struct PairIO<LBM_STORE_F32> {
     asm("" : "+v"(f), "+v"(g));
     const unsigned long long w = (unsigned long long)__float_as_uint(f) |
                                  ((unsigned long long)__float_as_uint(g) << 32);
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, w), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, w), r, voff, soff, CP);
   }
 };
 template <>
@@ -167,8 +173,9 @@ struct PairIO<LBM_STORE_F16_DEV> {
     v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
     return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v);
   }
+  template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
-    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, CP);
   }
 };
 template <>
@@ -190,8 +197,9 @@ struct PairIO<LBM_STORE_BF16_DEV> {
     u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
     return u >> 16;
   }
+  template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
-    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, CP);
   }
 };
 template <>
@@ -204,9 +212,10 @@ struct BufIO<LBM_STORE_F16_DEV> {
   static __device__ __forceinline__ float unpack(float w) {
     return (float)__builtin_bit_cast(_Float16, (unsigned short)__float_as_uint(w));
   }
+  template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
     v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, voff, soff, CP);
   }
 };
 template <>
@@ -217,11 +226,12 @@ struct BufIO<LBM_STORE_BF16_DEV> {
     return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff + IMM * 2, soff, 0));
   }
   static __device__ __forceinline__ float unpack(float w) { return __uint_as_float(__float_as_uint(w) << 16); }
+  template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float v) {
     v = fminf(fmaxf(v, -3.3895313892515355e38f), 3.3895313892515355e38f);
     uint32_t u = __float_as_uint(v);
     u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(u >> 16), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(u >> 16), r, voff, soff, CP);
   }
 };
 
@@ -439,9 +449,10 @@ __device__ __forceinline__ void sum_partials(const double* parts, int stride, in
 // outlet sources).  The value-level parts of the rules (anti-bounce-back
 // temperatures, Zou-He, convective blend) are applied when the row is
 // consumed.
-template <int S, int MODE, int KIND, bool TH, int NB>
+template <int S, int MODE, int KIND, bool TH, int NB, bool WT>
 struct TileRun {
   static constexpr bool EDGE = KIND != 0;  // rows near a wall or the periodic seam
+  static constexpr int CP = WT ? kWriteThrough : 0;  // cache policy of the state stores
   static constexpr bool XE = KIND == 2;    // the tile reaches column 0 or nx - 1
   static_assert(NB >= 2 && NB <= 4, "prefetch depth");
   using C = Codec<S>;
@@ -847,13 +858,13 @@ struct TileRun {
     if (MODE == MODE_STEP && !TH) {
       const int voff = OUT2 && !sb && interior ? ((r - 1) * pitch + x) * E2 : kDrop;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) BufIO<S>::st(rd, voff, sst[i], fnew[i]);
+      for (int i = 0; i < 9; ++i) BufIO<S>::template st<CP>(rd, voff, sst[i], fnew[i]);
     }
 
     // ---------------- stage 3: row c = r - 2: source and g collision
     if (MODE == MODE_STEP && TH && !ST3) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) PairIO<S>::st(rd, kDrop, sst[i], 0.f, 0.f);  // same count, see above
+      for (int i = 0; i < 9; ++i) PairIO<S>::template st<CP>(rd, kDrop, sst[i], 0.f, 0.f);  // same count, see above
     }
     if (MODE == MODE_STEP && TH && ST3) {
       const int cr = r - 2;
@@ -872,7 +883,7 @@ struct TileRun {
       collide_g(D, ck, c_dT, T, c_uax, c_uay, phi, ks);
       const int voff = interior ? (cr * pitch + x) * E2 : kDrop;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) PairIO<S>::st(rd, voff, sst[i], fc[i], ks[i]);
+      for (int i = 0; i < 9; ++i) PairIO<S>::template st<CP>(rd, voff, sst[i], fc[i], ks[i]);
     }
 
     // ---------------- rotate: d <- c <- b <- a
@@ -1033,7 +1044,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 // on both the cache-resident and the HBM-resident channel.
 constexpr int kDepthInterior = 2;
 
-template <int S, int MODE>
+template <int S, int MODE, bool WT>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void step_kernel(
     const Tile* __restrict__ tiles, int ntiles, const FinEntry* __restrict__ fins, int nfin,
     int gphase) {
@@ -1053,13 +1064,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) void
     const int kind = tl.kind;
     const int k = MODE == MODE_STEP ? (kind & 3) : ((kind >> 2) & 3);
     if (kind & kTileIsothermal) {
-      if (k == kTileColumnEdge) TileRun<S, MODE, 2, false, 2>(tl, gphase).run();
-      else if (k == kTileRowEdge) TileRun<S, MODE, 1, false, 2>(tl, gphase).run();
-      else TileRun<S, MODE, 0, false, kDepthInterior>(tl, gphase).run();
+      if (k == kTileColumnEdge) TileRun<S, MODE, 2, false, 2, WT>(tl, gphase).run();
+      else if (k == kTileRowEdge) TileRun<S, MODE, 1, false, 2, WT>(tl, gphase).run();
+      else TileRun<S, MODE, 0, false, kDepthInterior, WT>(tl, gphase).run();
     } else {
-      if (k == kTileColumnEdge) TileRun<S, MODE, 2, true, 2>(tl, gphase).run();
-      else if (k == kTileRowEdge) TileRun<S, MODE, 1, true, 2>(tl, gphase).run();
-      else TileRun<S, MODE, 0, true, kDepthInterior>(tl, gphase).run();
+      if (k == kTileColumnEdge) TileRun<S, MODE, 2, true, 2, WT>(tl, gphase).run();
+      else if (k == kTileRowEdge) TileRun<S, MODE, 1, true, 2, WT>(tl, gphase).run();
+      else TileRun<S, MODE, 0, true, kDepthInterior, WT>(tl, gphase).run();
     }
   }
 }
@@ -1186,11 +1197,17 @@ __global__ __launch_bounds__(256) void copy_kernel(vf4* __restrict__ dst, const 
   }
 
 hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, const FinEntry* fins,
-                           int nfin, int grid, int phase, hipStream_t s) {
+                           int nfin, int grid, int phase, bool write_through, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (grid <= 0 || grid > ntiles) grid = ntiles;
   grid += (nfin + 7) & ~7;
-#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_STEP>), dim3(grid), dim3(kWave), 0, s, tiles, ntiles, fins, nfin, phase)
+#define L(SS)                                                                                              \
+  if (write_through)                                                                                      \
+    hipLaunchKernelGGL((step_kernel<SS, MODE_STEP, true>), dim3(grid), dim3(kWave), 0, s, tiles, ntiles, fins, \
+                       nfin, phase);                                                                      \
+  else                                                                                                    \
+    hipLaunchKernelGGL((step_kernel<SS, MODE_STEP, false>), dim3(grid), dim3(kWave), 0, s, tiles, ntiles, fins, \
+                       nfin, phase);
   DISPATCH_STORE(storage, L)
 #undef L
   return hipGetLastError();
@@ -1198,7 +1215,7 @@ hipError_t lbm_launch_step(int storage, const Tile* tiles, int ntiles, const Fin
 
 hipError_t lbm_launch_readout(int storage, const Tile* tiles, int ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_READOUT>), dim3(ntiles), dim3(kWave), 0, s, tiles, ntiles, (const FinEntry*)nullptr, 0, phase)
+#define L(SS) hipLaunchKernelGGL((step_kernel<SS, MODE_READOUT, false>), dim3(ntiles), dim3(kWave), 0, s, tiles, ntiles, (const FinEntry*)nullptr, 0, phase)
   DISPATCH_STORE(storage, L)
 #undef L
   return hipGetLastError();

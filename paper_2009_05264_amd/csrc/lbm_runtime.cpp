@@ -292,6 +292,8 @@ extern "C" int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, 
   if (!d) return lbm_fail(LBM_E_NOMEM, "host allocation failed");
   d->P = *p;
   d->rows = 0;  // automatic
+  d->state_ab = 2 * L.state_bytes;
+  d->write_through = d->state_ab <= kWriteThroughMaxBytes;
   {
     // SIMDs of the current device (four per compute unit), for the tile shape
     int dev = 0, cus = 0;
@@ -588,7 +590,8 @@ extern "C" int lbm_init_fields_noalloc(lbm_domain* d, const double* rho0, const 
 int lbm_enqueue_steps(lbm_domain* d, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
     const int phase = (int)((d->step + k) & 1) ^ d->host.parity;
-    HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->fins_d, kFin, d->grid, phase, d->stream));
+    HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->fins_d, kFin, d->grid, phase,
+                             d->write_through, d->stream));
   }
   d->step += nsteps;
   return LBM_OK;

@@ -34,6 +34,8 @@ struct lbm_domain {
   int simds = 1024;  // SIMDs of the device (automatic tile rows)
   int device = 0;    // HIP device the domain was created on
   int batch_rows = 0;  // automatic rows chosen for the batch the domain is in (0: its own choice)
+  size_t state_ab = 0;  // bytes of the A/B state
+  bool write_through = false;  // state_ab <= kWriteThroughMaxBytes
   float* psiw_d[2] = {nullptr, nullptr};
   float* Tw_d[2] = {nullptr, nullptr};
   int* heater_d = nullptr;

@@ -24,14 +24,16 @@ import argparse
 import csv
 import glob
 import hashlib
+import re
 import json
 import os
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-# the step kernel and the host code that shapes its tiles
-KERNEL_SRC = [os.path.join(HERE, "csrc", "lbm_kernels.hip"), os.path.join(HERE, "csrc", "lbm_tiles.cpp")]
+# the step kernel, the host code that shapes its tiles, and the header with
+# the store-policy threshold
+KERNEL_SRC = [os.path.join(HERE, "csrc", f) for f in ("lbm_kernels.hip", "lbm_tiles.cpp", "lbm_internal.h")]
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
 
 
@@ -59,7 +61,7 @@ def counter(dirname: str, name: str):
         if r["Counter_Name"] != name:
             continue
         k = r["Kernel_Name"]
-        if "step_kernel<" in k and ", 0>" in k:
+        if re.search(r"step_kernel<\d+, 0(, (true|false))?>", k):  # storage, MODE_STEP[, store policy]
             step.append(float(r["Counter_Value"]))
         elif "copy_kernel" in k:
             copy.append(float(r["Counter_Value"]))
@@ -90,7 +92,7 @@ def main():
     w_scale = copy_bytes / (w_copy * 1024.0)
     rd = f_step * 1024.0 * f_scale
     wr = w_step * 1024.0 * w_scale
-    step = [k for k in ks if "step_kernel<" in k[0] and ", 0>" in k[0]]
+    step = [k for k in ks if re.search(r"step_kernel<\d+, 0(, (true|false))?>", k[0])]
     avg_ns = step[0][2] if step else float("nan")
 
     lines = [f"# step_kernel, workload {args.workload}, storage {args.storage}", "",
