@@ -18,6 +18,9 @@ FLAGS = [
     # boundary instantiations of the step then round every node identically,
     # so results do not depend on the tile shape
     "-ffp-contract=on",
+    # the kernels' first arguments arrive in SGPRs at wave start instead of
+    # through a scalar load (1600x200 channel: 12.17 -> 11.89 us per step)
+    "-mllvm", "-amdgpu-kernarg-preload-count=8",
     "-Wall", "-Wno-unused-function",
 ]
 
