@@ -301,7 +301,7 @@ typedef struct {
   int64_t queued, running, done;
   size_t resident_bytes, peak_resident_bytes;
   double lups;          /* lattice updates completed by the server        */
-  double busy_seconds;  /* host time spent inside device quanta           */
+  double busy_seconds;  /* device time of the quanta (events around each) */
   int64_t failed;       /* requests in LBM_REQ_FAILED                     */
 } lbm_server_info;
 
@@ -313,9 +313,20 @@ int lbm_server_create(size_t hbm_cap_bytes, int max_slots, int64_t quantum_steps
 /* LBM_E_CAP if the request alone exceeds the cap (it is not queued). */
 int lbm_server_submit(lbm_server* s, const lbm_params* p, const lbm_request* r, int64_t step_budget,
                       uint64_t* req_id);
-/* One admission + quantum + retirement round; *running (may be NULL)
- * receives the number of requests still running. */
+/* One admission + quantum + retirement round, waiting for the quantum (a
+ * quantum left on the device by lbm_server_pump_async is waited for and
+ * retired first); *running (may be NULL) receives the number of requests
+ * still running. */
 int lbm_server_pump(lbm_server* s, int* running);
+/* The same round without waiting: if a quantum is on the device and has not
+ * completed (an event recorded after it is queried), returns at once with
+ * *in_flight = 1; otherwise retires it (step 3), admits (step 1) and
+ * launches the next quantum (step 2) without waiting for it.  Requests
+ * submitted while a quantum runs are admitted when it has been retired, so
+ * a host loop that calls this between submissions records arrival times as
+ * they happen.  Completion times are taken when the retiring call sees the
+ * event complete.  *running and *in_flight may be NULL. */
+int lbm_server_pump_async(lbm_server* s, int* running, int* in_flight);
 /* *state = LBM_REQ_*; *time_to_solution_s (may be NULL) = completion minus
  * arrival in seconds once done, else -1.  LBM_REQ_FAILED: the request could
  * not be started (its lbm_create/lbm_init_fields error), or its density or

@@ -8,7 +8,10 @@
 // next quantum (continuous batching).  A request whose fields turn
 // non-finite is failed at the end of the quantum in which that happens and
 // its memory freed; the others go on unaffected (each domain keeps its own
-// state and reductions).
+// state and reductions).  lbm_server_pump waits for its quantum;
+// lbm_server_pump_async launches it and returns, and a later call retires
+// it once an event recorded after it has completed, so the host can take in
+// arrivals while the device works.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,6 +71,12 @@ struct lbm_server {
   int64_t done = 0, failed = 0;
   double lups = 0.0, busy = 0.0;
   uint64_t next_id = 1;
+  // the quantum on the device, if any: its steps and nodes, and events
+  // recorded before and after it on the server's stream
+  bool inflight = false;
+  int64_t inflight_q = 0;
+  double inflight_nodes = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 extern "C" int lbm_admission_plan(const size_t* footprints, int n, size_t cap, size_t used,
@@ -184,9 +193,11 @@ extern "C" int lbm_server_submit(lbm_server* s, const lbm_params* p, const lbm_r
   return LBM_OK;
 }
 
-extern "C" int lbm_server_pump(lbm_server* s, int* running) {
-  if (!s) return lbm_fail(LBM_E_INVALID, "server is NULL");
-  // admission, in arrival order, by footprint and free slots
+// Admission, in arrival order, by footprint and free slots; the batch is
+// rebuilt when the running set changed.  Then one quantum of the running
+// requests is launched (not waited for).  *launched: whether one was.
+static int launch_quantum(lbm_server* s, bool* launched) {
+  *launched = false;
   bool changed = false;
   if (!s->queue.empty() && (int)s->active.size() < s->max_slots) {
     std::vector<size_t> fps;
@@ -218,10 +229,7 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
       }
     }
   }
-  if (s->active.empty()) {
-    if (running) *running = 0;
-    return LBM_OK;
-  }
+  if (s->active.empty()) return LBM_OK;
   if (changed || !s->batch) {
     int rc = drop_batch(s);
     if (rc) return rc;
@@ -238,20 +246,38 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
     q = std::min(q, r.remaining);
     nodes += (double)r.P.nx * r.P.ny;
   }
-  const double t0 = now_s();
+  if (!s->ev0) {
+    HIPCHECK(hipEventCreate(&s->ev0));
+    HIPCHECK(hipEventCreate(&s->ev1));
+  }
+  HIPCHECK(hipEventRecord(s->ev0, s->stream));
   int rc = lbm_batch_step(s->batch, q);
-  if (!rc) rc = lbm_batch_sync(s->batch);
   if (rc) return rc;
+  HIPCHECK(hipEventRecord(s->ev1, s->stream));
+  s->inflight = true;
+  s->inflight_q = q;
+  s->inflight_nodes = nodes;
+  *launched = true;
+  return LBM_OK;
+}
+
+// Retirement of the quantum on the device, which has completed: budgets,
+// the non-finite check, requests done or failed.
+static int finish_quantum(lbm_server* s) {
+  s->inflight = false;
   const double t1 = now_s();
-  s->busy += t1 - t0;
-  s->lups += nodes * (double)q;
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+  s->busy += 1e-3 * (double)ms;
+  const int64_t q = s->inflight_q;
+  s->lups += s->inflight_nodes * (double)q;
   std::vector<uint64_t> still;
   bool retired = false;
   for (uint64_t id : s->active) {
     Request& r = s->reqs[id];
     r.remaining -= q;
     int bad = 0;
-    rc = lbm_nonfinite_seen(r.dom, &bad);
+    int rc = lbm_nonfinite_seen(r.dom, &bad);
     if (rc) return rc;
     if (bad) {
       r.state = LBM_REQ_FAILED;
@@ -271,7 +297,7 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
     }
   }
   if (retired) {
-    rc = drop_batch(s);  // releases the finished domains for read-out
+    int rc = drop_batch(s);  // releases the finished domains for read-out
     if (rc) return rc;
     for (uint64_t id : s->active) {
       Request& r = s->reqs[id];
@@ -279,8 +305,44 @@ extern "C" int lbm_server_pump(lbm_server* s, int* running) {
     }
   }
   s->active.swap(still);
-  if (running) *running = (int)s->active.size();
   return LBM_OK;
+}
+
+// Waits for the quantum on the device, if any, and retires it.
+static int settle(lbm_server* s) {
+  if (!s->inflight) return LBM_OK;
+  HIPCHECK(hipEventSynchronize(s->ev1));
+  return finish_quantum(s);
+}
+
+extern "C" int lbm_server_pump(lbm_server* s, int* running) {
+  if (!s) return lbm_fail(LBM_E_INVALID, "server is NULL");
+  int rc = settle(s);
+  bool launched = false;
+  if (!rc) rc = launch_quantum(s, &launched);
+  if (!rc && launched) rc = settle(s);
+  if (running) *running = (int)s->active.size();
+  return rc;
+}
+
+extern "C" int lbm_server_pump_async(lbm_server* s, int* running, int* in_flight) {
+  if (!s) return lbm_fail(LBM_E_INVALID, "server is NULL");
+  int rc = LBM_OK;
+  if (s->inflight) {
+    const hipError_t e = hipEventQuery(s->ev1);
+    if (e == hipErrorNotReady) {
+      if (running) *running = (int)s->active.size();
+      if (in_flight) *in_flight = 1;
+      return LBM_OK;
+    }
+    if (e != hipSuccess) return lbm_fail(LBM_E_DEVICE, "hipEventQuery failed: %s", hipGetErrorString(e));
+    rc = finish_quantum(s);
+  }
+  bool launched = false;
+  if (!rc) rc = launch_quantum(s, &launched);
+  if (running) *running = (int)s->active.size();
+  if (in_flight) *in_flight = s->inflight ? 1 : 0;
+  return rc;
 }
 
 extern "C" int lbm_server_poll(lbm_server* s, uint64_t id, int* state, double* time_to_solution_s) {
@@ -335,6 +397,10 @@ extern "C" int lbm_server_cancel(lbm_server* s, uint64_t id) {
   auto it = s->reqs.find(id);
   if (it == s->reqs.end()) return lbm_fail(LBM_E_INVALID, "unknown request %llu", (unsigned long long)id);
   Request& r = it->second;
+  if (r.state == LBM_REQ_RUNNING) {
+    int rc = settle(s);  // the quantum on the device first (it may finish or fail the request)
+    if (rc) return rc;
+  }
   if (r.state == LBM_REQ_QUEUED) {
     s->queue.erase(std::find(s->queue.begin(), s->queue.end(), id));
   } else if (r.state == LBM_REQ_RUNNING) {
@@ -364,8 +430,11 @@ extern "C" int lbm_server_stats(lbm_server* s, lbm_server_info* out) {
 
 extern "C" int lbm_server_destroy(lbm_server* s) {
   if (!s) return LBM_OK;
+  if (s->inflight) (void)hipEventSynchronize(s->ev1);
   (void)drop_batch(s);
   for (auto& kv : s->reqs) free_request(s, kv.second);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
   return LBM_OK;

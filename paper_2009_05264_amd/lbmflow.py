@@ -110,6 +110,7 @@ def lib():
             "lbm_server_submit": (C.c_int, [vp, C.POINTER(Params), C.POINTER(Request), C.c_int64,
                                             C.POINTER(C.c_uint64)]),
             "lbm_server_pump": (C.c_int, [vp, C.POINTER(C.c_int)]),
+            "lbm_server_pump_async": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
             "lbm_server_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int), dp]),
             "lbm_server_read_fields": (C.c_int, [vp, C.c_uint64, dp, dp, dp, dp]),
             "lbm_server_read_diag": (C.c_int, [vp, C.c_uint64, C.POINTER(Diag)]),
@@ -334,6 +335,12 @@ class Server:
         n = C.c_int()
         _check(lib().lbm_server_pump(self.h, C.byref(n)))
         return n.value
+
+    def pump_async(self) -> tuple[int, bool]:
+        """Non-blocking round: (requests running, a quantum is on the device)."""
+        n, f = C.c_int(), C.c_int()
+        _check(lib().lbm_server_pump_async(self.h, C.byref(n), C.byref(f)))
+        return n.value, bool(f.value)
 
     def poll(self, rid: int):
         st, t = C.c_int(), C.c_double()

@@ -6,9 +6,12 @@ Ly in {50, 100, 200}, u_in ~ U[0.002, 0.01], superheat ~ U[0.05, 0.2],
 contact angle ~ U[30, 120] degrees through the wall-density calibration
 table) with step budgets ~ U{lo..hi}, FP16-deviation
 storage with probability p16, and arrive with exponential gaps (seeded).
-The host loop submits every request whose arrival time has passed, then runs
-one server quantum; a request that arrives while others are on the device
-joins them at the next quantum.  Reports aggregate MLUPS (lattice updates /
+The host loop submits every request whose arrival time has passed and calls
+the server's non-blocking pump, which retires a finished quantum, admits and
+launches the next one; so arrivals are recorded as they happen, also while a
+quantum runs, and a request that arrives while others are on the device
+joins them at the next quantum (--blocking: the waiting pump instead, under
+which an arrival is only submitted once the quantum on the device is over).  Reports aggregate MLUPS (lattice updates /
 makespan), p50/p99 time to solution of the completed requests, the requests
 the server failed (fields turned non-finite; they are retired and freed
 while the others go on), and optionally checks sampled requests against the
@@ -56,7 +59,7 @@ def params_of(L, W, cfg, storage):
 
 
 def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0, quantum=500,
-               slots=512, check=0, stream=None):
+               slots=512, check=0, stream=None, blocking=False):
     import workloads as W
     from paper_2009_05264_amd import lbmflow as L
 
@@ -81,7 +84,10 @@ def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0,
                              T_init=ia["T_u"], noise=ia["noise"], seed=ia["seed"])
             ids[rid] = nxt
             nxt += 1
-        running = srv.pump()
+        if blocking:
+            running, in_flight = srv.pump(), False
+        else:
+            running, in_flight = srv.pump_async()
         for rid, k in list(ids.items()):
             st, t = srv.poll(rid)
             if st == L.REQ_FAILED:
@@ -99,13 +105,15 @@ def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0,
                 del ids[rid]
         if running == 0 and not ids and nxt < n:
             time.sleep(max(0.0, min(0.05, reqs[nxt][0] - (time.perf_counter() - t0))))
+        elif in_flight:
+            time.sleep(2e-4)
     makespan = time.perf_counter() - t0
     info = srv.stats()
     srv.close()
     lups = info["lups"]  # lattice updates the device did (failed requests up to their failure)
     t = np.array([tts[k] for k in range(n) if tts[k] is not None])
     out = {"requests": n, "rate_per_s": rate, "budget_range": [lo, hi], "p_fp16": p16, "seed": seed,
-           "cap_GB": cap_gb, "quantum_steps": quantum,
+           "cap_GB": cap_gb, "quantum_steps": quantum, "pump": "blocking" if blocking else "async",
            "aggregate_MLUPS": round(lups / makespan / 1e6, 1), "makespan_s": round(makespan, 2),
            "device_busy_s": round(info["busy_seconds"], 2),
            "tts_p50_s": round(float(np.percentile(t, 50)), 3), "tts_p99_s": round(float(np.percentile(t, 99)), 3),
@@ -140,13 +148,14 @@ def main():
     ap.add_argument("--cap-gb", type=float, default=200.0)
     ap.add_argument("--quantum", type=int, default=500)
     ap.add_argument("--check", type=int, default=16)
+    ap.add_argument("--blocking", action="store_true", help="the waiting pump (lbm_server_pump)")
     args = ap.parse_args()
     import torch
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
     res = run_stream(args.requests, args.rate, args.budget_lo, args.budget_hi, args.p_fp16, args.seed,
-                     args.cap_gb, args.quantum, check=args.check)
+                     args.cap_gb, args.quantum, check=args.check, blocking=args.blocking)
     print(json.dumps(res), flush=True)
 
 

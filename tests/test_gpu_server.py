@@ -1,6 +1,8 @@
 """GPU tests of the serving loop (lbm_server_*): requests of different sizes,
 parameters and storage kinds arrive while others run, are admitted under a
 memory cap, and each result equals the same solve run alone."""
+import time
+
 import numpy as np
 import pytest
 
@@ -198,3 +200,57 @@ def test_non_finite_request_fails_alone(L):
         f_alone, _ = run_alone(L, cfg, storage, budget)
         for key in f_alone:
             assert np.array_equal(results[k][key], f_alone[key]), (k, key)
+
+
+def test_async_pump_takes_arrivals_while_a_quantum_runs(L):
+    """The non-blocking pump: it launches a quantum and returns with it on
+    the device; requests submitted meanwhile join at the next quantum; every
+    result equals the same solve run alone (bitwise); a blocking pump after
+    an asynchronous one settles the quantum left on the device."""
+    reqs = request_set()
+    srv = L.Server(1 << 34, max_slots=8, quantum=40)
+    print("case: server async pump", flush=True)
+    ids = {submit(L, srv, *reqs[k]): k for k in range(3)}
+    running, in_flight = srv.pump_async()
+    assert running == 3 and in_flight  # launched, not waited for
+    pending = list(range(3, len(reqs)))
+    results = {}
+    saw_submit_in_flight = False
+    for _ in range(200000):
+        if pending and in_flight:
+            k = pending.pop(0)
+            ids[submit(L, srv, *reqs[k])] = k  # arrives while a quantum runs
+            saw_submit_in_flight = True
+        running, in_flight = srv.pump_async()
+        for rid, k in list(ids.items()):
+            st, t = srv.poll(rid)
+            assert st != L.REQ_FAILED, k
+            if st == L.REQ_DONE and k not in results:
+                cfg = reqs[k][0]
+                results[k] = srv.fields(rid, cfg.nx, cfg.ny)
+                assert t > 0
+                srv.release(rid)
+        if not pending and running == 0 and not in_flight and srv.stats()["queued"] == 0:
+            break
+        if in_flight:
+            time.sleep(1e-4)
+    assert saw_submit_in_flight
+    info = srv.stats()
+    assert len(results) == len(reqs), (len(results), info)
+    assert info["done"] == len(reqs) and info["resident_bytes"] == 0
+    assert info["lups"] == pytest.approx(sum(c.nx * c.ny * b for c, _, b in reqs))
+    assert 0 < info["busy_seconds"]
+    for k, (cfg, storage, budget) in enumerate(reqs):
+        f_alone, _ = run_alone(L, cfg, storage, budget)
+        for key in f_alone:
+            assert np.array_equal(results[k][key], f_alone[key]), (k, key)
+    # a blocking pump settles what an asynchronous one left running
+    cfg, storage, _ = reqs[0]
+    rid = submit(L, srv, cfg, storage, 80)
+    running, in_flight = srv.pump_async()
+    assert in_flight
+    srv.pump()  # retires the first quantum (40 steps), runs and retires the second
+    assert srv.poll(rid)[0] == L.REQ_DONE
+    f_alone, _ = run_alone(L, cfg, storage, 80)
+    assert np.array_equal(srv.fields(rid, cfg.nx, cfg.ny)["rho"], f_alone["rho"])
+    srv.close()
