@@ -114,6 +114,11 @@ typedef struct {
   double psi_clamped;  /* nodes where p - rho/3 > 0 made psi imaginary     */
   double nonfinite;    /* nodes with non-finite rho or T                   */
   double p_in, p_out;  /* EOS pressure at (0, ny/2) and (nx-1, ny/2)       */
+  double nu_heater;    /* heater Nusselt number, ny / (T_h - T_in) x        */
+                       /* heater_q / (heater cells), T_h the mean wall      */
+                       /* temperature of the heater cells of the wall map   */
+                       /* in force when read; 0 without heater cells        */
+  double dp;           /* centreline pressure drop p_in - p_out            */
 } lbm_diag;
 
 const char* lbm_last_error(void);

@@ -651,6 +651,34 @@ extern "C" int lbm_read_fields(lbm_domain* d, double* rho, double* ux, double* u
   return LBM_OK;
 }
 
+// One diagnostics record from the reduced sums v[kPartials], with the two
+// derived numbers: the heater Nusselt number Nu_h = ny / (T_h - T_in) x the
+// mean over the heater cells of (T_h - T(x, 0)) / (1/2) (T_h the mean wall
+// temperature of the heater cells of the current wall map) and the
+// centreline pressure drop p_in - p_out.
+static void fill_diag(const lbm_domain* d, int64_t step, const double* v, lbm_diag* out) {
+  out->step = step;
+  out->mass = v[P_MASS];
+  out->energy = v[P_ENERGY];
+  out->heater_q = v[P_HEATQ];
+  out->vapor_cells = v[P_VAPOR];
+  out->psi_clamped = v[P_CLAMP];
+  out->nonfinite = v[P_NONFINITE];
+  out->p_in = v[P_PIN];
+  out->p_out = v[P_POUT];
+  int nh = 0;
+  double th = 0.0;
+  if (d->P.bc_y == LBM_BCY_WALLS)
+    for (int x = 0; x < d->P.nx; ++x)
+      if (d->heater_h[x]) {
+        ++nh;
+        th += d->Tw_h[0][x];
+      }
+  const double dT = nh > 0 ? th / nh - d->P.T_in : 0.0;
+  out->nu_heater = nh > 0 && dT != 0.0 ? (double)d->P.ny / dT * v[P_HEATQ] / nh : 0.0;
+  out->dp = v[P_PIN] - v[P_POUT];
+}
+
 extern "C" int lbm_read_diag(lbm_domain* d, lbm_diag* out) {
   if (!d || !out) return lbm_fail(LBM_E_INVALID, "NULL argument");
   int rc = readout(d);
@@ -660,15 +688,7 @@ extern "C" int lbm_read_diag(lbm_domain* d, lbm_diag* out) {
   double h[kPartials];
   HIPCHECK(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, d->stream));
   HIPCHECK(hipStreamSynchronize(d->stream));
-  out->step = d->step;
-  out->mass = h[P_MASS];
-  out->energy = h[P_ENERGY];
-  out->heater_q = h[P_HEATQ];
-  out->vapor_cells = h[P_VAPOR];
-  out->psi_clamped = h[P_CLAMP];
-  out->nonfinite = h[P_NONFINITE];
-  out->p_in = h[P_PIN];
-  out->p_out = h[P_POUT];
+  fill_diag(d, d->step, h, out);
   return LBM_OK;
 }
 
@@ -686,15 +706,7 @@ extern "C" int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n) {
   const int off = (int)valid.size() - k;
   for (int i = 0; i < k; ++i) {
     const DiagRec& r = valid[off + i];
-    out[i].step = r.step;
-    out[i].mass = r.v[P_MASS];
-    out[i].energy = r.v[P_ENERGY];
-    out[i].heater_q = r.v[P_HEATQ];
-    out[i].vapor_cells = r.v[P_VAPOR];
-    out[i].psi_clamped = r.v[P_CLAMP];
-    out[i].nonfinite = r.v[P_NONFINITE];
-    out[i].p_in = r.v[P_PIN];
-    out[i].p_out = r.v[P_POUT];
+    fill_diag(d, r.step, r.v, &out[i]);
   }
   *n = k;
   return LBM_OK;

@@ -48,6 +48,7 @@ int main(void) {
   CHECK(lbm_read_diag(d, &g));
   printf("step %lld: mass %.6f energy %.6f heater flux %.6e vapour cells %.0f\n", (long long)g.step,
          g.mass, g.energy, g.heater_q, g.vapor_cells);
+  printf("heater Nusselt number %.4f, centreline pressure drop %.6e\n", g.nu_heater, g.dp);
   double* f = malloc(sizeof(double) * 4 * p.nx * p.ny);
   CHECK(lbm_read_fields(d, f, f + p.nx * p.ny, f + 2 * p.nx * p.ny, f + 3 * p.nx * p.ny));
   const double* T = f + 3 * p.nx * p.ny;

@@ -42,7 +42,8 @@ class Params(C.Structure):
 
 class Diag(C.Structure):
     _fields_ = [("step", C.c_int64)] + [(n, C.c_double) for n in (
-        "mass", "energy", "heater_q", "vapor_cells", "psi_clamped", "nonfinite", "p_in", "p_out")]
+        "mass", "energy", "heater_q", "vapor_cells", "psi_clamped", "nonfinite", "p_in", "p_out", "nu_heater",
+        "dp")]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

@@ -39,7 +39,7 @@ def test_binding_struct_sizes():
 
     txt = open(HEADER).read()
     assert C.sizeof(L.Params) == 8 * 4 + 26 * 8
-    assert C.sizeof(L.Diag) == 8 + 8 * 8
+    assert C.sizeof(L.Diag) == 8 + 10 * 8
     assert "double rho_ref, T_ref;" in txt
     # rho_out, then G_wet, close lbm_params
     assert txt.index("double rho_out;") > txt.index("double rho_ref, T_ref;")

@@ -110,6 +110,16 @@ def test_channel_diagnostics(L):
     assert gd["p_in"] == pytest.approx(od["p_in"], rel=1e-4, abs=1e-6)
     assert gd["p_out"] == pytest.approx(od["p_out"], rel=1e-4, abs=1e-6)
     assert gd["step"] == 60
+    # the derived numbers: heater Nusselt number from the oracle's heater flux
+    # (R25: ny / (T_h - T_in) x mean over heater cells of (T_h - T) / (1/2))
+    # and the centreline pressure drop, in the read-out and in the history
+    n_heat = int(cfg.heater().sum())
+    nu_o = cfg.ny / (cfg.T_heater - cfg.T_in) * od["heater_q"] / n_heat
+    assert gd["nu_heater"] == pytest.approx(nu_o, rel=1e-3, abs=1e-6)
+    assert gd["dp"] == pytest.approx(od["p_in"] - od["p_out"], rel=1e-3, abs=1e-6)
+    h = d.diag_history(4)[-1]
+    assert h["nu_heater"] == pytest.approx(cfg.ny / (cfg.T_heater - cfg.T_in) * h["heater_q"] / n_heat, rel=1e-12)
+    assert h["dp"] == h["p_in"] - h["p_out"]
 
 
 @pytest.mark.parametrize("nx,ny,bcx,bcy", [
