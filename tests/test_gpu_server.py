@@ -166,21 +166,28 @@ def test_cancel_and_cap(L):
     srv.close()
 
 
-def test_non_finite_request_fails_alone(L):
+@pytest.mark.parametrize("pump", ["blocking", "async"])
+def test_non_finite_request_fails_alone(L, pump):
     """Failure isolation: among three ordinary requests, one whose buoyancy
     (g_a = -1 in lattice units) drives its fields non-finite within a few
     dozen steps is retired as failed (LBM_E_NAN) at the end of that quantum,
     with its memory freed; the other three finish and equal their solo runs
-    bitwise."""
+    bitwise.  With either pump."""
     reqs = request_set()[:3]
     bad = W.Channel(nx=67, ny=13, heater_len=5, seed=3, extra=dict(ga_y=-1.0))
     srv = L.Server(1 << 34, max_slots=8, quantum=40)
-    print("case: server with one diverging request", flush=True)
+    print(f"case: server with one diverging request, {pump} pump", flush=True)
     ids = {submit(L, srv, *r): k for k, r in enumerate(reqs)}
     bad_id = submit(L, srv, bad, "F32_DEV", 120)
     results = {}
-    for _ in range(100):
-        running = srv.pump()
+    for _ in range(100000):
+        if pump == "async":
+            running, in_flight = srv.pump_async()
+            if in_flight:
+                time.sleep(1e-4)
+                continue
+        else:
+            running = srv.pump()
         for rid, k in ids.items():
             st, _ = srv.poll(rid)
             assert st != L.REQ_FAILED, k
