@@ -52,6 +52,10 @@ static void strip_segments(int ny, int rows, bool column_edge, std::vector<std::
 // takes the column-edge path (inlet, outlet or periodic seam).
 static bool strip_is_column_edge(int x0, int nx) { return !(x0 >= 3 && x0 + kWave - 2 < nx); }
 
+static bool half_storage(int storage) {
+  return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV;
+}
+
 long long lbm_tile_count(int nx, int ny, int rows) {
   const int strips = (nx + kStripInterior - 1) / kStripInterior;
   std::vector<std::pair<int, int>> seg;
@@ -69,11 +73,23 @@ long long lbm_tile_count(int nx, int ny, int rows) {
 // the shortest tiles (4 to 7 rows) whose waves, with the finalizer waves,
 // fit on the SIMDs at once.  Larger domains run in several rounds, bound by
 // memory traffic, where 7 rows measured best with FP32 storage (1-4 % ahead
-// of 8 from 1600x400 to 8192x2048) and 8 rows with 16-bit storage.
-static int lbm_auto_rows(int nx, int ny, int simds, bool half) {
+// of 8 from 1600x400 to 8192x2048); with 16-bit storage 8 rows while the
+// state fits the Infinity Cache (12 rows 10-27 % slower from 1600x400 to
+// 3200x800) and 12 rows once it streams from HBM (8192x2048 304.5 -> 288.2
+// us per step, 8192x1024 151.5 -> 149.4 us).
+static int lbm_auto_rows(int nx, int ny, int simds, bool half, bool streaming) {
   for (int r = 4; r < 8; ++r)
     if (lbm_tile_count(nx, ny, r) + kFin <= simds) return r;
-  return half ? 8 : 7;
+  return half ? (streaming ? 12 : 8) : 7;
+}
+
+// Whether a thermal domain's A/B state streams from HBM (the write-back
+// store policy of the runtime, kWriteThroughMaxBytes).
+static bool streams_from_hbm(int nx, int ny, int storage) {
+  const size_t elem = half_storage(storage) ? 2 : 4;
+  const size_t plane = (size_t)((nx + 31) / 32 * 32) * (size_t)ny;
+  const size_t state = (18 * plane * elem + 255) / 256 * 256;
+  return 2 * state > kWriteThroughMaxBytes;
 }
 
 // The tile list of an nx x ny domain at `rows` rows per tile, in launch
@@ -110,10 +126,6 @@ static void plan_tiles(int nx, int ny, int rows, bool isothermal, std::vector<Ti
   });
 }
 
-static bool half_storage(int storage) {
-  return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV;
-}
-
 extern "C" int lbm_tile_plan(int nx, int ny, int storage, int simds, int rows, int* rows_used, int* x0,
                              int* y0, int* y1, int max, int* n) {
   if (nx < 3 || ny < 3 || rows < 0 || max < 0 || !n || (max > 0 && (!x0 || !y0 || !y1)))
@@ -121,7 +133,8 @@ extern "C" int lbm_tile_plan(int nx, int ny, int storage, int simds, int rows, i
   if (storage < LBM_STORE_F32 || storage > LBM_STORE_BF16_DEV)
     return lbm_fail(LBM_E_INVALID, "unknown storage %d", storage);
   const int r = rows > 0 ? std::max(kMinTileRows, rows)
-                         : lbm_auto_rows(nx, ny, simds > 0 ? simds : 1024, half_storage(storage));
+                         : lbm_auto_rows(nx, ny, simds > 0 ? simds : 1024, half_storage(storage),
+                                         streams_from_hbm(nx, ny, storage));
   std::vector<Tile> tiles;
   plan_tiles(nx, ny, r, false, tiles);
   for (int i = 0; i < max && i < (int)tiles.size(); ++i) {
@@ -139,7 +152,8 @@ int lbm_build_tiles(lbm_domain* d) {
   const int nx = d->P.nx, ny = d->P.ny;
   const int rows = d->rows > 0         ? std::max(kMinTileRows, d->rows)
                    : d->batch_rows > 0 ? d->batch_rows
-                                       : lbm_auto_rows(nx, ny, d->simds, half_storage(d->P.storage));
+                                       : lbm_auto_rows(nx, ny, d->simds, half_storage(d->P.storage),
+                                                       !d->write_through);
   plan_tiles(nx, ny, rows, d->P.isothermal != 0, d->tiles_h);
   for (Tile& tl : d->tiles_h) tl.d = d->dev;
   for (size_t i = 0; i < d->tiles_h.size(); ++i) d->tiles_h[i].local = (int)i;

@@ -72,8 +72,12 @@ def test_automatic_heights(L):
     assert L.tile_plan(200, 50)[0] == 4 and L.tile_plan(800, 200)[0] == 5
     # several rounds of waves: 7 rows with FP32 storage, 8 with 16-bit storage
     assert L.tile_plan(8192, 1024)[0] == 7
-    assert L.tile_plan(8192, 1024, storage=L.STORE_F16_DEV)[0] == 8
-    assert L.tile_plan(8192, 1024, storage=L.STORE_BF16_DEV)[0] == 8
+    # 16-bit storage: 8 rows while the state fits the Infinity Cache, 12 once
+    # it streams from HBM (A/B state above 224 MiB)
+    assert L.tile_plan(1600, 400, storage=L.STORE_F16_DEV)[0] == 8
+    assert L.tile_plan(3200, 800, storage=L.STORE_F16_DEV)[0] == 8
+    assert L.tile_plan(8192, 1024, storage=L.STORE_F16_DEV)[0] == 12
+    assert L.tile_plan(8192, 1024, storage=L.STORE_BF16_DEV)[0] == 12
     # shortest height whose tiles and 16 finalizer waves fit the SIMDs at once
     for nx, ny, simds in ((1600, 200, 1024), (800, 200, 1024), (1200, 200, 1024), (1600, 200, 2048),
                           (400, 100, 256), (3000, 300, 4096)):
