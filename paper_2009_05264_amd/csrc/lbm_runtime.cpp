@@ -651,21 +651,9 @@ extern "C" int lbm_read_fields(lbm_domain* d, double* rho, double* ux, double* u
   return LBM_OK;
 }
 
-// One diagnostics record from the reduced sums v[kPartials], with the two
-// derived numbers: the heater Nusselt number Nu_h = ny / (T_h - T_in) x the
-// mean over the heater cells of (T_h - T(x, 0)) / (1/2) (T_h the mean wall
-// temperature of the heater cells of the current wall map) and the
-// centreline pressure drop p_in - p_out.
-static void fill_diag(const lbm_domain* d, int64_t step, const double* v, lbm_diag* out) {
-  out->step = step;
-  out->mass = v[P_MASS];
-  out->energy = v[P_ENERGY];
-  out->heater_q = v[P_HEATQ];
-  out->vapor_cells = v[P_VAPOR];
-  out->psi_clamped = v[P_CLAMP];
-  out->nonfinite = v[P_NONFINITE];
-  out->p_in = v[P_PIN];
-  out->p_out = v[P_POUT];
+// Heater cells of the current wall map and ny / (T_h - T_in) / cells, T_h
+// their mean wall temperature (0 without heater cells).
+static double nusselt_factor(const lbm_domain* d) {
   int nh = 0;
   double th = 0.0;
   if (d->P.bc_y == LBM_BCY_WALLS)
@@ -675,7 +663,24 @@ static void fill_diag(const lbm_domain* d, int64_t step, const double* v, lbm_di
         th += d->Tw_h[0][x];
       }
   const double dT = nh > 0 ? th / nh - d->P.T_in : 0.0;
-  out->nu_heater = nh > 0 && dT != 0.0 ? (double)d->P.ny / dT * v[P_HEATQ] / nh : 0.0;
+  return nh > 0 && dT != 0.0 ? (double)d->P.ny / dT / nh : 0.0;
+}
+
+// One diagnostics record from the reduced sums v[kPartials], with the two
+// derived numbers: the heater Nusselt number Nu_h = ny / (T_h - T_in) x the
+// mean over the heater cells of (T_h - T(x, 0)) / (1/2) = nu_factor x the
+// heater flux sum, and the centreline pressure drop p_in - p_out.
+static void fill_diag(double nu_factor, int64_t step, const double* v, lbm_diag* out) {
+  out->step = step;
+  out->mass = v[P_MASS];
+  out->energy = v[P_ENERGY];
+  out->heater_q = v[P_HEATQ];
+  out->vapor_cells = v[P_VAPOR];
+  out->psi_clamped = v[P_CLAMP];
+  out->nonfinite = v[P_NONFINITE];
+  out->p_in = v[P_PIN];
+  out->p_out = v[P_POUT];
+  out->nu_heater = nu_factor * v[P_HEATQ];
   out->dp = v[P_PIN] - v[P_POUT];
 }
 
@@ -688,7 +693,7 @@ extern "C" int lbm_read_diag(lbm_domain* d, lbm_diag* out) {
   double h[kPartials];
   HIPCHECK(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, d->stream));
   HIPCHECK(hipStreamSynchronize(d->stream));
-  fill_diag(d, d->step, h, out);
+  fill_diag(nusselt_factor(d), d->step, h, out);
   return LBM_OK;
 }
 
@@ -704,9 +709,10 @@ extern "C" int lbm_diag_history(lbm_domain* d, lbm_diag* out, int max, int* n) {
   std::sort(valid.begin(), valid.end(), [](const DiagRec& a, const DiagRec& b) { return a.step < b.step; });
   const int k = std::min<int>(max, (int)valid.size());
   const int off = (int)valid.size() - k;
+  const double nu_factor = nusselt_factor(d);
   for (int i = 0; i < k; ++i) {
     const DiagRec& r = valid[off + i];
-    fill_diag(d, r.step, r.v, &out[i]);
+    fill_diag(nu_factor, r.step, r.v, &out[i]);
   }
   *n = k;
   return LBM_OK;
