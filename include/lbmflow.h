@@ -139,8 +139,9 @@ int lbm_required_bytes(const lbm_params* p, size_t* bytes);
 /* Create a domain on the current HIP device.  Validates p (LBM_E_INVALID):
  * nx, ny >= 3; tau_f, tau_g > 1/2; 0 < s_* < 2; c_v > 0; |u_in| < 0.1;
  * temperatures > 0; the state buffer addressable with 32-bit offsets
- * (11 planes of pitch x (ny + 2) elements under 2 GB: about 24 M nodes with
- * FP32 thermal storage, 48 M with FP16/BF16).  dev_mem/dev_bytes: see
+ * (11 pitch x (ny + 2) elements under 2 GB, pitch = nx rounded up to 32: the
+ * 9 direction planes of every row with a margin; about 24 M nodes with FP32
+ * thermal storage, 48 M with FP16/BF16).  dev_mem/dev_bytes: see
  * Conventions. */
 int lbm_create(const lbm_params* p, void* hip_stream, void* dev_mem, size_t dev_bytes,
                lbm_domain** out);

@@ -165,7 +165,10 @@ static int build_groups(lbm_batch* b) {
   for (lbm_domain* d : b->doms) {
     state_by[d->P.storage] += d->state_ab;
     auto& v = by[d->P.storage];
+    const size_t at = v.size();
     v.insert(v.end(), d->tiles_h.begin(), d->tiles_h.end());
+    // the batch's launch phase is offset by the domain's parity
+    for (size_t i = at; i < v.size(); ++i) v[i].parity = d->host.parity;
     for (int f = 0; f < kFin; ++f) fby[d->P.storage].push_back(FinEntry{d->dev, f, 0});
   }
   for (auto& kv : by) {

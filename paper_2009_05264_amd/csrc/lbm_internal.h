@@ -39,7 +39,7 @@ struct DiagRec {
 struct DevDomain {
   int nx, ny, pitch, storage;
   int bc_x, bc_y, isothermal, single_phase;
-  long long plane;  // elements per distribution plane (pitch * ny)
+  long long row;    // elements per row of the state: its 9 direction planes of pitch elements
   int ntiles, pad0;
   // EOS / force constants
   float a, b, R, kappa;
@@ -56,7 +56,8 @@ struct DevDomain {
   float dro;      // rho_ref - rho_out of the constant-pressure outlet
   float pad4;
   // buffers
-  void* buf[2];         // state A/B: 9 planes [ny][pitch] of (f_i, g_i) pairs (f_i alone when isothermal)
+  void* buf[2];         // state A/B: [ny][9][pitch] (row, direction plane, column) of (f_i, g_i)
+                        // pairs (f_i alone when isothermal)
   float* fold[2];       // convective-outlet memory [3][ny] (deviation form), A/B; unused by the
                         // constant-pressure outlet
   const float* psiw[2]; // pseudopotential of the false wall density, S and N, [nx]
@@ -90,17 +91,31 @@ struct FinEntry {
 };
 
 // One tile of the step kernel: a 64-lane strip starting two columns left of
-// x0, covering rows [y0, y1).
-struct Tile {
+// x0, covering rows [y0, y1).  The record repeats the descriptor fields that
+// the first row loads need (state buffers, sizes, strides) and carries the
+// table's launch parity, so that a wave issues its first loads
+// one memory round trip after it starts (the tile record) instead of two
+// (the record, then the descriptor it points to).  One 64-byte line per
+// tile.
+struct alignas(64) Tile {
   DevDomain* d;
+  void* buf[2];  // the descriptor's state buffers A/B
   int x0, y0, y1;
   int local;  // tile index within its domain (partials slot); 0 = first tile
   // code path, chosen on the host so that a wave branches on its tile record
   // alone: bits 0-1 when stepping, bits 2-3 for read-out (kTileInterior,
   // kTileRowEdge, kTileColumnEdge); kTileIsothermal when the domain is
+  // isothermal
   int kind;
-  int pad;
+  // added to the launch phase: 0 in a domain's own table, the domain's
+  // descriptor parity in a batch's table (the buffer of the state being read
+  // is buf[launch phase ^ parity])
+  int parity;
+  int nx, ny;   // the descriptor's sizes
+  int ystride;  // elements from a row of a direction plane to the next (9 pitch)
+  int istride;  // elements from a direction plane to the next within a row (pitch)
 };
+static_assert(sizeof(Tile) == 64, "one tile record per 64-byte line");
 
 enum TileKind { kTileInterior = 0, kTileRowEdge = 1, kTileColumnEdge = 2, kTileIsothermal = 16 };
 

@@ -16,7 +16,9 @@
 // cross-lane shuffles.  No LDS, no barrier.  All arithmetic is FP32 on the
 // deviations f_i - w_i rho_ref, g_i - w_i T_ref; the HBM storage is FP32,
 // FP16 or BF16 (template parameter), one plane per direction holding the
-// (f_i, g_i) pair of every node (f_i alone for isothermal domains).
+// (f_i, g_i) pair of every node (f_i alone for isothermal domains); the
+// nine direction planes of a row are stored one after the other, so that
+// the rows a wave pulls and stores lie together in memory.
 //
 // Reductions for the diagnostics are fixed-order FP64: each tile writes its
 // partial sums; in the next launch kFin finalizer waves per domain reduce
@@ -465,7 +467,8 @@ struct TileRun {
   const float* fold;
   float* fold_dst;
   Rsrc rs, rd;
-  int pitch, sst[9];  // plane byte offsets
+  int pitch;    // elements from a row to the next in one direction plane
+  int sst[9];   // byte offsets of the direction planes within a row
   int kb;             // extra base offset of the pull resource (column-edge tiles)
   float gbar;     // rho_ref - mean density (formed in run(), first used by stage 2)
   unsigned long long mtot, mprev;  // running mass totals: one slot per lane; this tile's previous reading
@@ -504,9 +507,11 @@ struct TileRun {
   __device__ __forceinline__ TileRun(const Tile AS4& t, int gphase)
       : D(*(const DevDomain AS4*)t.d), tl(t) {
     lane = threadIdx.x & (kWave - 1);
-    phase = gphase ^ D.parity;
-    nx = D.nx;
-    ny = D.ny;
+    // The first row loads need only the tile record: buffers, sizes and
+    // strides come from it, not from the descriptor it points to.
+    phase = gphase ^ tl.parity;
+    nx = tl.nx;
+    ny = tl.ny;
     chan = XE && D.bc_x != LBM_BCX_PERIODIC;
     walls = EDGE && D.bc_y == LBM_BCY_WALLS;
     fold = D.fold[phase];
@@ -519,23 +524,19 @@ struct TileRun {
     has_out = chan && tl.x0 + kWave - 3 >= nx - 1;
     mL = XE && xc == 0 ? -1 : 0;
     mR = XE && xc == nx - 1 ? -1 : 0;
-    pitch = D.pitch;
-    const int plane = (int)D.plane;
+    pitch = tl.ystride;
+    const int plane = tl.istride;
 #pragma unroll
     for (int i = 0; i < 9; ++i) sst[i] = i * plane * E2;
     // Column-edge tiles of thermal domains redirect some inlet sources to a
     // lower plane (a negative per-lane offset): their resource base sits two
     // planes lower still, so every per-lane offset stays non-negative.
     kb = XE && TH ? 2 * sst[1] : 0;
-    rs = make_rsrc((const char*)D.buf[phase] - kb - (pitch + 1) * E2);
-    rd = make_rsrc(D.buf[phase ^ 1]);
-    // mean density of the previous state: the running mass totals the
-    // previous launch added to (one slot per lane) and this tile's reading
-    // of them two launches back, combined in run() once the first rows are
-    // in flight.  Plain loads: both were last written in earlier launches,
-    // whose writes the kernel boundary makes visible.
-    mtot = lane < kAccSlots ? D.macc[phase ^ 1][lane * kAccStride] : 0ull;
-    mprev = D.mhist[phase ^ 1][tl.local];
+    // both pointers at fixed offsets of the record, then selected
+    void* const b0 = tl.buf[0];
+    void* const b1 = tl.buf[1];
+    rs = make_rsrc((const char*)(phase ? b1 : b0) - kb - (pitch + 1) * E2);
+    rd = make_rsrc(phase ? b0 : b1);
     r_end = MODE == MODE_STEP ? tl.y1 + 1 : tl.y1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) bh[i] = bk[i] = ck[i] = fc[i] = 0.f;
@@ -959,6 +960,18 @@ struct TileRun {
     // fifth.
     const int y0 = tl.y0;
     fetch<0>(y0 - 2);
+    // Mean density of the previous state: the running mass totals the
+    // previous launch added to (one slot per lane) and this tile's reading
+    // of them two launches back, combined below once the first rows are in
+    // flight.  Issued after the first row's loads, which need the tile
+    // record alone, and by every lane (no branch ahead of them).  Plain
+    // loads: both were last written in earlier launches, whose writes the
+    // kernel boundary makes visible.
+    {
+      const unsigned long long w = D.macc[phase ^ 1][min(lane, kAccSlots - 1) * kAccStride];
+      mtot = lane < kAccSlots ? w : 0ull;
+      mprev = D.mhist[phase ^ 1][tl.local];
+    }
     if constexpr (NB >= 3) fetch<1>(y0 - 1);
     if constexpr (NB >= 4) fetch<2>(y0);
     iter<false, false, false, true, 0>(y0 - 2);
@@ -1109,13 +1122,13 @@ __global__ void init_kernel(DevDomain D, const double* rho0, const double* T0, d
       r = rho_u * (1.0 + noise * (2.0 * u - 1.0));
     }
     const double t = T0 ? T0[id] : T_u;
-    const uint32_t idx = (uint32_t)(y * D.pitch + x);
     const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    // plane i holds f_i (isothermal) or the (f_i, g_i) pair of each node
+    // plane i holds f_i (isothermal) or the (f_i, g_i) pair of each node;
+    // the planes of row y follow each other from element 9 pitch y
     const uint32_t E2 = D.isothermal ? C::E : 2 * C::E;
     for (int i = 0; i < 9; ++i) {
-      const uint32_t o = (uint32_t)(i * (uint32_t)D.plane + idx) * E2;
+      const uint32_t o = ((uint32_t)(9 * y + i) * (uint32_t)D.pitch + (uint32_t)x) * E2;
       C::st(buf, o, (float)(W[i] * (r - (double)D.rho_ref)));
       if (!D.isothermal) C::st(buf, o + C::E, (float)(W[i] * (t - (double)D.T_ref)));
     }

@@ -105,8 +105,10 @@ int validate(const lbm_params* p) {
   if (p->bc_x == LBM_BCX_CHANNEL_P && !(p->rho_out > 0))
     return lbm_fail(LBM_E_INVALID, "a constant-pressure outlet needs rho_out > 0");
   {
-    // The kernels address a state buffer with 32-bit byte offsets: 9 planes
-    // plus the two-plane base shift of the boundary pull must stay below 2 GB.
+    // The kernels address a state buffer with 32-bit byte offsets: its ny
+    // rows of 9 direction planes, plus the base shift of the boundary pull
+    // (a row, a column and two planes), must stay below 2 GB (checked with
+    // two planes of margin per row).
     const bool half = p->storage == LBM_STORE_F16_DEV || p->storage == LBM_STORE_BF16_DEV;
     const double e2 = (half ? 2.0 : 4.0) * (p->isothermal ? 1.0 : 2.0);
     const double pitch = (double)((p->nx + 31) / 32 * 32);
@@ -139,9 +141,10 @@ int max_tiles(const lbm_params& p) {
 
 Layout layout_of(const lbm_params& p) {
   Layout L{};
-  const size_t planes = p.isothermal ? 9 : 18;
-  const size_t plane = (size_t)pitch_of(p.nx) * p.ny;
-  L.state_bytes = align_up(planes * plane * elem_bytes(p.storage), 256);
+  // ny rows of 9 direction planes of pitch (f, g) pairs (f alone when isothermal)
+  const size_t per_node = p.isothermal ? 9 : 18;
+  const size_t nodes = (size_t)pitch_of(p.nx) * p.ny;
+  L.state_bytes = align_up(per_node * nodes * elem_bytes(p.storage), 256);
   L.fold_bytes = align_up(3 * (size_t)p.ny * sizeof(float), 256);
   const size_t mt = max_tiles(p);
   size_t o = 0;
@@ -237,7 +240,7 @@ void fill_desc(lbm_domain* d) {
   D.bc_y = p.bc_y;
   D.isothermal = p.isothermal;
   D.single_phase = p.single_phase;
-  D.plane = (long long)D.pitch * p.ny;
+  D.row = 9LL * D.pitch;
   D.a = (float)p.a;
   D.b = (float)p.b;
   D.R = (float)p.R;
@@ -589,7 +592,8 @@ extern "C" int lbm_init_fields_noalloc(lbm_domain* d, const double* rho0, const 
 
 int lbm_enqueue_steps(lbm_domain* d, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
-    const int phase = (int)((d->step + k) & 1) ^ d->host.parity;
+    // the domain's own tile table has parity 0 (stepping is refused in a batch)
+    const int phase = (int)((d->step + k) & 1);
     HIPCHECK(lbm_launch_step(d->P.storage, d->tiles_d, d->ntiles, d->fins_d, kFin, d->grid, phase,
                              d->write_through, d->stream));
   }
@@ -616,9 +620,9 @@ extern "C" int64_t lbm_step_count(const lbm_domain* d) { return d ? d->step : -1
 static int readout(lbm_domain* d) {
   if (!d->inited) return lbm_fail(LBM_E_STATE, "lbm_init_fields has not been called");
   HIPCHECK(wait_batch(d));
-  // the kernel adds the descriptor's parity: pass the phase that lands on step & 1
-  HIPCHECK(lbm_launch_readout(d->P.storage, d->tiles_d, d->ntiles,
-                              (int)(d->step & 1) ^ d->host.parity, d->stream));
+  // the domain's own tile table (parity 0), also while it is in a batch: the
+  // phase is the parity of the step whose state is read
+  HIPCHECK(lbm_launch_readout(d->P.storage, d->tiles_d, d->ntiles, (int)(d->step & 1), d->stream));
   return LBM_OK;
 }
 

@@ -155,8 +155,18 @@ int lbm_build_tiles(lbm_domain* d) {
                                        : lbm_auto_rows(nx, ny, d->simds, half_storage(d->P.storage),
                                                        !d->write_through);
   plan_tiles(nx, ny, rows, d->P.isothermal != 0, d->tiles_h);
-  for (Tile& tl : d->tiles_h) tl.d = d->dev;
-  for (size_t i = 0; i < d->tiles_h.size(); ++i) d->tiles_h[i].local = (int)i;
+  for (size_t i = 0; i < d->tiles_h.size(); ++i) {
+    Tile& tl = d->tiles_h[i];
+    tl.d = d->dev;
+    tl.local = (int)i;
+    tl.buf[0] = d->host.buf[0];
+    tl.buf[1] = d->host.buf[1];
+    tl.nx = d->host.nx;
+    tl.ny = d->host.ny;
+    tl.ystride = (int)d->host.row;
+    tl.istride = d->host.pitch;
+    tl.parity = 0;  // the domain's own table: launched with the step's own phase
+  }
   if ((int)d->tiles_h.size() > d->host.pstride)
     return lbm_fail(LBM_E_CAP, "tile table of %zu tiles exceeds its capacity %d", d->tiles_h.size(),
                     d->host.pstride);
