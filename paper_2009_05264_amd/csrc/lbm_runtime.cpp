@@ -111,7 +111,7 @@ int validate(const lbm_params* p) {
     // two planes of margin per row).
     const bool half = p->storage == LBM_STORE_F16_DEV || p->storage == LBM_STORE_BF16_DEV;
     const double e2 = (half ? 2.0 : 4.0) * (p->isothermal ? 1.0 : 2.0);
-    const double pitch = (double)((p->nx + 31) / 32 * 32);
+    const double pitch = (double)lbm_pitch(p->nx);
     if (11.0 * pitch * (p->ny + 2.0) * e2 > 2147483648.0 - 16777216.0)
       return lbm_fail(LBM_E_INVALID, "domain %d x %d too large for one state buffer (32-bit offsets)", p->nx,
                       p->ny);
@@ -130,7 +130,6 @@ struct Layout {
   size_t state_bytes, fold_bytes;
 };
 
-int pitch_of(int nx) { return (nx + 31) / 32 * 32; }
 int elem_bytes(int storage) { return storage == LBM_STORE_F16_DEV || storage == LBM_STORE_BF16_DEV ? 2 : 4; }
 int max_tiles(const lbm_params& p) {
   // column-edge strips (at most two) may be cut into single rows
@@ -143,7 +142,7 @@ Layout layout_of(const lbm_params& p) {
   Layout L{};
   // ny rows of 9 direction planes of pitch (f, g) pairs (f alone when isothermal)
   const size_t per_node = p.isothermal ? 9 : 18;
-  const size_t nodes = (size_t)pitch_of(p.nx) * p.ny;
+  const size_t nodes = (size_t)lbm_pitch(p.nx) * p.ny;
   L.state_bytes = align_up(per_node * nodes * elem_bytes(p.storage), 256);
   L.fold_bytes = align_up(3 * (size_t)p.ny * sizeof(float), 256);
   const size_t mt = max_tiles(p);
@@ -234,13 +233,12 @@ void fill_desc(lbm_domain* d) {
   rates(p, &s_nu, &s_e, &s_eps, &s_q);
   D.nx = p.nx;
   D.ny = p.ny;
-  D.pitch = pitch_of(p.nx);
+  D.pitch = lbm_pitch(p.nx);
   D.storage = p.storage;
   D.bc_x = p.bc_x;
   D.bc_y = p.bc_y;
   D.isothermal = p.isothermal;
   D.single_phase = p.single_phase;
-  D.row = 9LL * D.pitch;
   D.a = (float)p.a;
   D.b = (float)p.b;
   D.R = (float)p.R;

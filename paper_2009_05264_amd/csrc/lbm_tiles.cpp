@@ -87,8 +87,8 @@ static int lbm_auto_rows(int nx, int ny, int simds, bool half, bool streaming) {
 // store policy of the runtime, kWriteThroughMaxBytes).
 static bool streams_from_hbm(int nx, int ny, int storage) {
   const size_t elem = half_storage(storage) ? 2 : 4;
-  const size_t plane = (size_t)((nx + 31) / 32 * 32) * (size_t)ny;
-  const size_t state = (18 * plane * elem + 255) / 256 * 256;
+  const size_t nodes = (size_t)lbm_pitch(nx) * (size_t)ny;
+  const size_t state = (18 * nodes * elem + 255) / 256 * 256;
   return 2 * state > kWriteThroughMaxBytes;
 }
 
@@ -163,7 +163,7 @@ int lbm_build_tiles(lbm_domain* d) {
     tl.buf[1] = d->host.buf[1];
     tl.nx = d->host.nx;
     tl.ny = d->host.ny;
-    tl.ystride = (int)d->host.row;
+    tl.ystride = 9 * d->host.pitch;  // a row holds its 9 direction planes
     tl.istride = d->host.pitch;
     tl.parity = 0;  // the domain's own table: launched with the step's own phase
   }
