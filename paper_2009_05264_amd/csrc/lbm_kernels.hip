@@ -379,10 +379,30 @@ __device__ __forceinline__ float shfl_up1(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(i, i, 0x138, 0xF, 0xF, false));  // wave_shr:1
 }
 
+// One DPP move of a double (both halves); lanes of rows outside ROWS get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the wavefront in a fixed order by DPP moves: two quad
+// permutations and the two mirrors leave every lane of a 16-lane row with
+// the row's sum; two row broadcasts then accumulate rows 0-3 into lane 63,
+// whose value every lane gets.  Called with every lane active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // Sum of v over lanes 0-15 (an inclusive scan along the first DPP row,
@@ -408,10 +428,15 @@ __device__ __forceinline__ unsigned long long to_fixed(double m) {
   return (unsigned long long)(long long)(fabs(m) < 1e9 ? m * kMassScale : 0.0);
 }
 
+// The same tree for 32-bit integers (exact).
 __device__ __forceinline__ int wave_sum_int(int v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Fixed-order sum of tiles [t0, t1) of SoA partial sums by one wave; every
@@ -986,7 +1011,7 @@ struct TileRun {
     iter<true, false, false, true, 2 % NB>(y0);
     iter<true, true, false, true, 3 % NB>(y0 + 1);
     steady<4 % NB>(y0 + 2);
-    // tile partial sums: FP64 in a fixed order (lane tree), the counts as
+    // tile partial sums: FP64 in a fixed order (DPP lane tree), the counts as
     // exact 32-bit integers; heater and pressure sums are zero off the edge
     // tiles (fewer cross-lane rounds at the end of every tile)
     double v[kPartials];
@@ -1004,7 +1029,6 @@ struct TileRun {
       for (int q = 0; q < kPartials; ++q) out[(long long)q * D.pstride] = v[q];
     }
     if (MODE == MODE_STEP && lane == 0 && v[P_NONFINITE] > 0.0) *D.nf_flag = 1;  // sticky, for the server
-    v[P_MASS] = MODE == MODE_STEP ? mass_tile : wave_sum(acc_mass);
   }
 };
 
