@@ -92,6 +92,10 @@ typedef const DevDomain AS4& DRef;
 // wave-uniform byte offset per distribution plane (SGPR) and one per-lane
 // byte offset per row (VGPR).
 typedef __amdgpu_buffer_rsrc_t Rsrc;
+// two-element vectors for the packed 16-bit conversions of the stores
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // Cache-policy operand of the state stores: 0 (default, write-back in the L2)
 // or kWriteThrough (SC1: agent-scope stores, which the L2 writes through);
 // the host picks one per launch from the size of the state it touches.
@@ -171,13 +175,13 @@ struct PairIO<LBM_STORE_F16_DEV> {
     f = (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xFFFFu));
     g = (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
   }
-  static __device__ __forceinline__ uint32_t enc(float v) {
-    v = fminf(fmaxf(v, -65504.f), 65504.f);  // saturate, round to nearest even
-    return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v);
-  }
+  // saturate, then round both to nearest even in one packed conversion
+  // (f in the low half)
   template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
-    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, CP);
+    const f32x2 v = {fminf(fmaxf(f, -65504.f), 65504.f), fminf(fmaxf(g, -65504.f), 65504.f)};
+    const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+    __builtin_amdgcn_raw_buffer_store_b32(w, r, voff, soff, CP);
   }
 };
 template <>
@@ -193,15 +197,14 @@ struct PairIO<LBM_STORE_BF16_DEV> {
     f = __uint_as_float(u << 16);
     g = __uint_as_float(u & 0xFFFF0000u);
   }
-  static __device__ __forceinline__ uint32_t enc(float v) {
-    v = fminf(fmaxf(v, -3.3895313892515355e38f), 3.3895313892515355e38f);
-    uint32_t u = __float_as_uint(v);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return u >> 16;
-  }
+  // saturate to the largest finite value, then round both to nearest even
+  // in one packed conversion (f in the low half)
   template <int CP>
   static __device__ __forceinline__ void st(Rsrc r, int voff, int soff, float f, float g) {
-    __builtin_amdgcn_raw_buffer_store_b32(enc(f) | (enc(g) << 16), r, voff, soff, CP);
+    constexpr float kMax = 3.3895313892515355e38f;
+    const f32x2 v = {fminf(fmaxf(f, -kMax), kMax), fminf(fmaxf(g, -kMax), kMax)};
+    const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+    __builtin_amdgcn_raw_buffer_store_b32(w, r, voff, soff, CP);
   }
 };
 template <>
