@@ -370,24 +370,35 @@ __device__ __forceinline__ void collide_g(DRef D, const float k[9], float dT, fl
   for (int i = 1; i < 9; ++i) ks[i] = keep * k[i] + WF[i] * (base + tT * cu[i] * (3.f + 4.5f * cu[i]));
 }
 
-// Neighbour exchange across the wavefront by DPP row moves: shfl_dn1 gives
-// lane i the value of lane i + 1, shfl_up1 that of lane i - 1; the end
-// lane without a source keeps its own value (as __shfl_down / __shfl_up).
+// Neighbour exchange across the wavefront by DPP wave shifts: shfl_dn1
+// gives lane i the value of lane i + 1, shfl_up1 that of lane i - 1; the
+// end lane without a source (63, resp. 0) reads 0.  Those are outer halo
+// lanes: what they form reaches only the other halo lane's stage 3, and
+// neither stores nor adds to the tile sums.  (A move with no previous
+// value to keep needs no copy of its source into the destination.)
 __device__ __forceinline__ float shfl_dn1(float v) {
-  const int i = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(i, i, 0x130, 0xF, 0xF, false));  // wave_shl:1
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));  // wave_shl:1
 }
 __device__ __forceinline__ float shfl_up1(float v) {
-  const int i = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(i, i, 0x138, 0xF, 0xF, false));  // wave_shr:1
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));  // wave_shr:1
 }
 
-// One DPP move of a double (both halves); lanes of rows outside ROWS get 0.
+// One DPP move of a 32-bit value; lanes of rows outside ROWS get 0 (a
+// move of all rows keeps no previous value, so it needs no copy).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+  if constexpr (ROWS == 0xF)
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+  else
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+
+// The same move of a double (both halves).
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_f64(double v) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xF, false);
+  const int lo = dpp_i32<CTRL, ROWS>((int)(unsigned)u);
+  const int hi = dpp_i32<CTRL, ROWS>((int)(unsigned)(u >> 32));
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
@@ -411,9 +422,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Sum of v over lanes 0-15 (an inclusive scan along the first DPP row,
 // whose last lane then holds the total), returned to every lane.
 __device__ __forceinline__ unsigned long long row0_sum_u64(unsigned long long v) {
+  // lanes without a source (the first of each row) read 0
   auto shr = [](unsigned long long x, auto ctrl) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, decltype(ctrl)::value, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), decltype(ctrl)::value, 0xF, 0xF, false);
+    const int lo = dpp_i32<decltype(ctrl)::value, 0xF>((int)(unsigned)x);
+    const int hi = dpp_i32<decltype(ctrl)::value, 0xF>((int)(unsigned)(x >> 32));
     return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
   };
   v += shr(v, std::integral_constant<int, 0x111>{});  // row_shr:1
@@ -433,12 +445,12 @@ __device__ __forceinline__ unsigned long long to_fixed(double m) {
 
 // The same tree for 32-bit integers (exact).
 __device__ __forceinline__ int wave_sum_int(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+  v += dpp_i32<0xB1, 0xF>(v);
+  v += dpp_i32<0x4E, 0xF>(v);
+  v += dpp_i32<0x141, 0xF>(v);
+  v += dpp_i32<0x140, 0xF>(v);
+  v += dpp_i32<0x142, 0xA>(v);
+  v += dpp_i32<0x143, 0xC>(v);
   return __builtin_amdgcn_readlane(v, 63);
 }
 
