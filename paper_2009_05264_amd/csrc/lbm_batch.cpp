@@ -32,14 +32,15 @@ void lbm_drop_graphs(lbm_domain* d) {
   d->graphs.clear();
 }
 
-// Launch pairs (phase 0 then phase 1) captured once and replayed: the
+// Launch pairs (phase p then phase p ^ 1) captured once and replayed: the
 // kernels take everything that changes from step to step from device memory.
-static int capture_pairs(hipStream_t s, GraphEntry* g, int pairs, int (*enqueue)(void*, int), void* ctx) {
+static int capture_pairs(hipStream_t s, GraphEntry* g, int pairs, int p, int (*enqueue)(void*, int),
+                         void* ctx) {
   HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   int rc = 0;
   for (int q = 0; q < pairs && !rc; ++q) {
-    rc = enqueue(ctx, 0);
-    if (!rc) rc = enqueue(ctx, 1);
+    rc = enqueue(ctx, p);
+    if (!rc) rc = enqueue(ctx, p ^ 1);
   }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s, &graph);
@@ -60,51 +61,72 @@ static int capture_pairs(hipStream_t s, GraphEntry* g, int pairs, int (*enqueue)
 }
 
 static int capture_pair(hipStream_t s, GraphEntry* g, int (*enqueue)(void*, int), void* ctx) {
-  return capture_pairs(s, g, 1, enqueue, ctx);
+  return capture_pairs(s, g, 1, 0, enqueue, ctx);
 }
 
-// Replay graphs of 2^k launch pairs, k < kGraphLevels.  One hipGraphLaunch
-// costs the host a few microseconds, more than a step of a small domain:
-// replaying two launches per graph left a ~2.5 us gap per step on a
-// 1600x200 channel, a graph of 32 launches none.  Any even step count is
-// replayed as repeats of the longest graph plus at most one graph of each
-// shorter length (its binary digits), so a call of n steps launches at most
-// n / 32 + 4 graphs.
-constexpr int kGraphLevels = 5;
+// Replay graphs of 2^k launch pairs, k < kGraphLevels, one set per start
+// phase (entry p * kGraphLevels + k).  Whatever is queued behind a graph
+// starts ~8 us after the graph's last kernel ends (kernel traces of the
+// 1600x200 channel; consecutive launches inside a graph, or plain launches,
+// start without a gap), so graphs are long: up to 256 launches, that start
+// paid once per 256 steps.  Any even step count is replayed as at most one
+// graph of each shorter length (the binary digits of its pairs) plus repeats
+// of the longest graph, so a call of n steps launches at most n / 256 + 7
+// graphs.
+constexpr int kGraphLevels = 8;
+
+// Calls shorter than this are launched one kernel at a time: the host
+// submits a launch faster than a step runs (measured with steps down to 7.6
+// us, a 200x50 channel), so plain launches leave no gaps, and a short call
+// would pay the start behind each of its graphs (20 steps of the 1600x200
+// channel from an idle device: 11.68 us per step with graphs, 11.13 with
+// plain launches).  Longer calls replay graphs, which keep the device fed
+// whatever the host does meanwhile.
+constexpr int64_t kGraphMinSteps = 64;
 
 // Captures the graphs a call needs (all of them when eager), before any of
 // them is launched: a capture never lands between launches of a call.
-static int ensure_graphs(hipStream_t s, std::vector<GraphEntry>& g, int64_t pairs, bool eager,
+static int ensure_graphs(hipStream_t s, std::vector<GraphEntry>& g, int64_t pairs, int p, bool eager,
                          int (*enqueue)(void*, int), void* ctx) {
-  if ((int)g.size() < kGraphLevels) g.resize(kGraphLevels);
+  if ((int)g.size() < 2 * kGraphLevels) g.resize(2 * kGraphLevels);
   const int top = kGraphLevels - 1;
-  for (int k = 0; k < kGraphLevels; ++k) {
-    const bool needed = k == top ? (pairs >> top) > 0 : ((pairs >> k) & 1) != 0;
-    if (g[k].exec || !(eager || needed)) continue;
-    int rc = capture_pairs(s, &g[k], 1 << k, enqueue, ctx);
-    if (rc) return rc;
-  }
+  for (int q = 0; q < 2; ++q)
+    for (int k = 0; k < kGraphLevels; ++k) {
+      const bool needed = q == p && (k == top ? (pairs >> top) > 0 : ((pairs >> k) & 1) != 0);
+      GraphEntry& e = g[q * kGraphLevels + k];
+      if (e.exec || !(eager || needed)) continue;
+      int rc = capture_pairs(s, &e, 1 << k, q, enqueue, ctx);
+      if (rc) return rc;
+    }
   return LBM_OK;
 }
 
-// Replays the even part of n steps from an even step; *done counts the
-// steps enqueued (the at most one step left over is the caller's).
-static int replay_steps(hipStream_t s, std::vector<GraphEntry>& g, int64_t n, bool eager,
+// Replays the even part of n steps, the first of launch phase p; *done
+// counts the steps enqueued (the at most one step left over is the
+// caller's).
+static int replay_steps(hipStream_t s, std::vector<GraphEntry>& g, int64_t n, int p, bool eager,
                         int (*enqueue)(void*, int), void* ctx, int64_t* done) {
   *done = 0;
   const int64_t pairs = n / 2;
   if (pairs == 0) return LBM_OK;
-  int rc = ensure_graphs(s, g, pairs, eager, enqueue, ctx);
+  int rc = ensure_graphs(s, g, pairs, p, eager, enqueue, ctx);
   if (rc) return rc;
   const int top = kGraphLevels - 1;
+  GraphEntry* set = &g[p * kGraphLevels];
   // shorter graphs first: the device starts on them while the host still
   // submits the longer ones
   for (int k = 0; k < top; ++k)
-    if ((pairs >> k) & 1) HIPCHECK(hipGraphLaunch(g[k].exec, s));
-  for (int64_t k = 0; k < (pairs >> top); ++k) HIPCHECK(hipGraphLaunch(g[top].exec, s));
+    if ((pairs >> k) & 1) HIPCHECK(hipGraphLaunch(set[k].exec, s));
+  for (int64_t k = 0; k < (pairs >> top); ++k) HIPCHECK(hipGraphLaunch(set[top].exec, s));
   *done = 2 * pairs;
   return LBM_OK;
 }
+
+// Single launches that open a call of n >= kGraphMinSteps steps: one when n
+// is odd, so that the replay graphs cover an even number of steps and end
+// the call (nothing of the call waits behind a graph), and a first pair, so
+// that the device starts on it before the first graph is submitted.
+static int64_t head_launches(int64_t n) { return 2 + (n & 1); }
 
 static int enqueue_domain_phase(void* ctx, int phase) {
   lbm_domain* d = (lbm_domain*)ctx;
@@ -115,27 +137,16 @@ static int enqueue_domain_phase(void* ctx, int phase) {
 
 int lbm_run_steps(lbm_domain* d, int64_t n) {
   if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch; step the batch");
-  if (n == 0) return ensure_graphs(d->stream, d->graphs, 0, true, enqueue_domain_phase, d);
-  if (n < 2) return lbm_enqueue_steps(d, n);
-  if (d->step & 1) {
-    int rc = lbm_enqueue_steps(d, 1);
-    if (rc) return rc;
-    --n;
-  }
-  // A call of six or more steps launches its first pair directly, so the
-  // device starts on it before the first graph is submitted (20 steps of a
-  // 1600x200 channel from an idle device: 11.83 -> 11.55 us per step).
-  if (n >= 6) {
-    int rc = lbm_enqueue_steps(d, 2);
-    if (rc) return rc;
-    n -= 2;
-  }
-  int64_t done = 0;
-  int rc = replay_steps(d->stream, d->graphs, n, true, enqueue_domain_phase, d, &done);
-  d->step += done;
+  if (n == 0) return ensure_graphs(d->stream, d->graphs, 0, 0, true, enqueue_domain_phase, d);
+  if (n < kGraphMinSteps) return lbm_enqueue_steps(d, n);
+  const int64_t head = head_launches(n);
+  int rc = lbm_enqueue_steps(d, head);
   if (rc) return rc;
-  if (n > done) return lbm_enqueue_steps(d, n - done);
-  return LBM_OK;
+  n -= head;
+  int64_t done = 0;
+  rc = replay_steps(d->stream, d->graphs, n, (int)(d->step & 1), true, enqueue_domain_phase, d, &done);
+  d->step += done;
+  return rc;
 }
 
 // ------------------------------------------------------------------ batches
@@ -153,7 +164,7 @@ struct lbm_batch {
     bool write_through = false;  // the group's A/B state is at most kWriteThroughMaxBytes
   };
   std::vector<Group> groups;
-  std::vector<GraphEntry> graphs;  // [k]: 2^k launch pairs
+  std::vector<GraphEntry> graphs;  // [p * kGraphLevels + k]: 2^k launch pairs from phase p
   GraphEntry probe;                // the autotuner's timing graph (one launch pair)
   bool eager = true;               // capture every replay graph on first use
   int64_t k = 0;  // steps done by the batch
@@ -413,20 +424,17 @@ void lbm_batch_lazy_graphs(lbm_batch* b) {
 extern "C" int lbm_batch_step(lbm_batch* b, int64_t n) {
   if (!b) return lbm_fail(LBM_E_INVALID, "batch is NULL");
   if (n < 0) return lbm_fail(LBM_E_INVALID, "nsteps must be >= 0");
-  if (n == 0) return ensure_graphs(b->stream, b->graphs, 0, true, enqueue_batch_phase, b);
-  if (n < 2) return batch_steps_plain(b, n);
-  if (b->k & 1) {
-    int rc = batch_steps_plain(b, 1);
-    if (rc) return rc;
-    --n;
-  }
+  if (n == 0) return ensure_graphs(b->stream, b->graphs, 0, 0, true, enqueue_batch_phase, b);
+  if (n < kGraphMinSteps) return batch_steps_plain(b, n);
+  const int64_t head = head_launches(n);
+  int rc = batch_steps_plain(b, head);
+  if (rc) return rc;
+  n -= head;
   int64_t done = 0;
-  int rc = replay_steps(b->stream, b->graphs, n, b->eager, enqueue_batch_phase, b, &done);
+  rc = replay_steps(b->stream, b->graphs, n, (int)(b->k & 1), b->eager, enqueue_batch_phase, b, &done);
   b->k += done;
   for (lbm_domain* d : b->doms) d->step += done;
-  if (rc) return rc;
-  if (n > done) return batch_steps_plain(b, n - done);
-  return LBM_OK;
+  return rc;
 }
 
 extern "C" int lbm_batch_sync(lbm_batch* b) {

@@ -45,7 +45,7 @@ struct lbm_domain {
   bool inited = false;
   bool in_batch = false;
   hipStream_t batch_stream = nullptr;  // stream the domain's batch runs on (while in one)
-  std::vector<GraphEntry> graphs;  // replay graphs of this domain: [k] 2^k launch pairs
+  std::vector<GraphEntry> graphs;  // replay graphs of this domain, by start phase and length (lbm_batch.cpp)
 };
 
 int lbm_fail(int code, const char* fmt, ...);

@@ -257,11 +257,12 @@ def test_tiling_invariance_ragged_bitwise(L):
 
 def test_repeatable_and_graph_equals_plain(L):
     """Same run twice is bitwise identical; 75 steps through the replayed
-    graphs (a first pair launched directly, 32-step and shorter graphs, a
-    single launch, from an odd start as well) equal 75 single launches."""
+    graphs (single launches first, then graphs of up to 64 launches starting
+    at an odd launch phase, or at an even one, then short calls launched
+    singly) equal 75 single launches."""
     cfg = W.c1()
     out = []
-    for split in ((75,), (1,) * 75, (75,), (1, 33, 9, 32)):
+    for split in ((75,), (1,) * 75, (75,), (1, 33, 9, 32), (64, 11)):
         d = make_gpu(L, cfg)
         d.init(**cfg.init_args())
         for n in split:
@@ -340,7 +341,7 @@ def test_batch_equals_solo(L):
         d = make_gpu(L, c)
         d.init(**c.init_args())
         d.step(1)  # odd start: exercises the parity offsets
-        d.step(40)
+        d.step(70)
         solo.append(d.fields())
     doms = []
     for c in cfgs:
@@ -354,7 +355,7 @@ def test_batch_equals_solo(L):
         with pytest.raises(L.LbmError) as e:
             call()
         assert e.value.code == L.LBM_E_STATE
-    b.step(40)  # one 32-step graph, four pairs
+    b.step(70)  # a first pair, then replay graphs of 64 and 4 launches
     # a read-out of a domain stepped on another stream waits for the batch
     early = doms[2].fields()
     for k in early:
@@ -363,14 +364,14 @@ def test_batch_equals_solo(L):
     b.close()
     for s, d in zip(solo, doms):
         f = d.fields()
-        assert d.steps == 41
+        assert d.steps == 71
         for k in f:
             assert np.array_equal(f[k], s[k]), k
     # 25 more steps alone on both sides: fields and diagnostics agree
     for c, d in zip(cfgs, doms):
         ref = make_gpu(L, c)
         ref.init(**c.init_args())
-        ref.step(41)
+        ref.step(71)
         ref.step(25)
         d.step(25)
         fr, fd = ref.fields(), d.fields()
