@@ -65,7 +65,7 @@ def make_domain(L, W, cfg, storage, stream):
 def time_domain(torch, d, steps, warmup):
     """Wall time and HIP-event time (on the domain's stream) of `steps` steps.
     The warm-up steps run first; step(0) then captures whichever replay
-    graphs are not captured yet, so the timed call only launches them, and
+    graphs are not captured yet, so the timed call captures nothing, and
     the timing events are recorded once before the timed region."""
     d.step(warmup)
     d.step(0)
@@ -163,7 +163,7 @@ def main():
     nodes = cfg.nx * cfg.ny
     d = make_domain(L, W, cfg, storage, stream)
     wall, ev = time_domain(torch, d, args.steps, args.warmup)
-    launch_s = ev / args.steps  # HIP events around the timed graph replay, per launch
+    launch_s = ev / args.steps  # HIP events around the timed launches, per launch
     diag = d.diag()
     d.close()
     mlups = nodes * args.steps / wall / 1e6
@@ -189,9 +189,10 @@ def main():
                      "avg_launch_us": round(1e6 * launch_s, 3),
                      "rocprof_kernel_us": None if prof is None else round(prof["kernel_trace_avg_us"], 3),
                      "note": "avg_launch_us: HIP events on the kernels' stream around the timed steps "
-                             "(replay graphs of 2-32 launches captured during warm-up, plus a single launch "
-                             "for an odd step) divided by the launches, i.e. kernel execution plus any gap "
-                             "between dependent launches and the first launch's submission; "
+                             "(single launches for a call under 64 steps; else one or two single launches, "
+                             "then replay graphs of up to 256 launches captured during warm-up) divided by "
+                             "the launches, i.e. kernel execution plus any gap between dependent launches "
+                             "and the first launch's submission; "
                              "rocprof_kernel_us is the kernel-trace execution time of the committed profile. "
                              "The 1600x200 FP32 A/B state (46 MB) fits the 256 MB Infinity Cache"},
         "health": {"nonfinite": diag["nonfinite"], "psi_clamped": diag["psi_clamped"]},
