@@ -184,14 +184,15 @@ int lbm_init_fields_noalloc(lbm_domain* d, const double* rho0, const double* T0,
 
 /* Enqueue nsteps time steps (the update of Sec. 2 summarised at the top of
  * this file) on the domain's stream (nsteps >= 0): one kernel launch per
- * step.  From 2 steps on they are replayed from captured hipGraphs of 2, 4,
- * 8, 16 and 32 launches (all five captured by the first call of 2 or more
- * steps, before any is launched; dropped when the tiling changes): repeats
- * of the 32-launch graph, then at most one of each shorter one, plus a
- * single launch for an odd step.  nsteps == 0 enqueues nothing and captures
- * the five graphs if they are not captured yet (so that a timed call
- * captures nothing).  Results are bitwise the same however nsteps is
- * split. */
+ * step.  A call of fewer than 64 steps launches them one by one.  A longer
+ * call launches one or two singly (so that an even count remains), then
+ * replays captured hipGraphs of 2 to 256 launches, one set per start phase
+ * (all captured by the first call of 64 or more steps, before any is
+ * launched; dropped when the tiling changes): at most one graph of each
+ * shorter length, then repeats of the 256-launch graph.  nsteps == 0
+ * enqueues nothing and captures the graphs that are not captured yet (so
+ * that a timed call captures nothing).  Results are bitwise the same
+ * however nsteps is split. */
 int lbm_step(lbm_domain* d, int64_t nsteps);
 /* Waits for the domain's stream (and its batch's, while it is in one). */
 int lbm_sync(lbm_domain* d);
