@@ -12,9 +12,11 @@ rho_mid) is labelled into 8-connected components.  Per run:
   that sample is the equivalent diameter D = 2 sqrt(A / pi) of the
   component(s) that covered the heater at the previous sample;
 * lift: first sample at which such a component no longer touches the
-  bottom wall row (departure into the stream), with its diameter.
+  bottom wall row (departure into the stream), with its diameter;
+* nonfinite: first sample with a non-finite density, if any.
 
     python3 paper_2009_05264_amd/sweeps.py --steps 18000
+    python3 paper_2009_05264_amd/sweeps.py --c2 --steps 100000 --K 500
 """
 from __future__ import annotations
 
@@ -38,9 +40,13 @@ class Tracker:
         self.prev = None  # mask of the components covering the heater at the previous sample
         self.onset = self.leave = self.lift = None
         self.D_leave = self.D_lift = None
+        self.nonfinite = None
 
     def sample(self, step: int, rho: np.ndarray):
         from scipy import ndimage
+
+        if self.nonfinite is None and not np.isfinite(rho).all():
+            self.nonfinite = step
 
         vap = rho < self.mid
         lab, _ = ndimage.label(vap, structure=np.ones((3, 3)))
@@ -64,7 +70,7 @@ class Tracker:
 
     def result(self):
         return {"onset": self.onset, "leave": self.leave, "D_leave": self.D_leave, "lift": self.lift,
-                "D_lift": self.D_lift}
+                "D_lift": self.D_lift, "nonfinite": self.nonfinite}
 
 
 def runs_default():
@@ -80,6 +86,15 @@ def runs_default():
     for rw in (3.0, 3.4, 4.2):  # ~83, 71, 49 degrees (60 at 3.8), sessile-drop table at 0.86 Tc
         out.append(("rho_w", rw, W.Channel(rho_w=rw)))
     return out
+
+
+def runs_c2():
+    """(label, value, Channel): the nine 1600x200 channels of the benchmark
+    sweep, superheat in {0.05, 0.1, 0.15} T_sat x u_in in {0.002, 0.005,
+    0.01}, 80-cell heater."""
+    import workloads as W
+
+    return [("c2", f"superheat {s} u_in {u}", W.c2(s, u)) for s, u in W.C2_SWEEP]
 
 
 def run(steps: int = 18000, K: int = 50, storage: str = "F32_DEV", runs=None, fields: bool = False):
@@ -143,8 +158,9 @@ def main():
     ap.add_argument("--steps", type=int, default=18000)
     ap.add_argument("--K", type=int, default=50)
     ap.add_argument("--storage", default="F32_DEV")
+    ap.add_argument("--c2", action="store_true", help="the nine 1600x200 channels of the benchmark sweep")
     a = ap.parse_args()
-    print(json.dumps(run(a.steps, a.K, a.storage)), flush=True)
+    print(json.dumps(run(a.steps, a.K, a.storage, runs=runs_c2() if a.c2 else None)), flush=True)
 
 
 if __name__ == "__main__":

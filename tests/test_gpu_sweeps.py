@@ -83,3 +83,37 @@ def test_regime_map_slug_at_low_reynolds():
     print(res["runs"], flush=True)
     assert reg[(0.48, 1.4)]["regime"] == "slug"
     assert all(reg[(1.92, t)]["regime"] == "attached bubble" for t in (1.2, 1.4))
+
+
+def test_benchmark_channel_sweep_trends():
+    """The nine 1600x200 channels of the benchmark sweep (superheat 0.05,
+    0.1, 0.15 T_sat x u_in 0.002, 0.005, 0.01; 80-cell heater) as one batch
+    over 30 000 steps (Sec. 3B-3C trends at the benchmark size): all stay
+    finite (the first of them turns non-finite near step 38 000);
+    nucleation comes earlier at a higher superheat and later at a
+    higher inlet velocity; at 0.15 T_sat the first departing bubble is
+    smaller at the higher inlet velocity."""
+    import math
+
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_05264_amd import sweeps
+
+    print("case: batched sweep, 9 channels 1600x200, 30000 steps", flush=True)
+    res = sweeps.run(steps=30000, K=500, runs=sweeps.runs_c2())
+    rs = res["runs"]
+    print([{k: r[k] for k in ("value", "onset", "lift", "D_lift", "nonfinite")} for r in rs], flush=True)
+    assert all(r["finite"] and r["nonfinite"] is None for r in rs)
+
+    def onset(s, u):
+        r = next(r for r in rs if r["value"] == f"superheat {s} u_in {u}")
+        return math.inf if r["onset"] is None else r["onset"]
+
+    for u in (0.002, 0.005):
+        assert onset(0.15, u) < onset(0.1, u) <= onset(0.05, u)
+    assert onset(0.15, 0.002) < onset(0.15, 0.005) < onset(0.15, 0.01)
+    lift = {u: next(r for r in rs if r["value"] == f"superheat 0.15 u_in {u}") for u in (0.002, 0.005)}
+    assert lift[0.002]["D_lift"] is not None and lift[0.005]["D_lift"] is not None
+    assert lift[0.002]["D_lift"] > lift[0.005]["D_lift"]
