@@ -234,28 +234,33 @@ static void drop_batch_graph(lbm_batch* b) {
 // chains on a SIMD.  A step of a batch that is not bound by memory traffic
 // lasts about (rounds of waves on the SIMDs) x (row steps of a chain,
 // rows + 4): the height (4 to 8 rows) that minimises this product is taken,
-// ties going to the taller tiles (fewer halo rows).  The choice is undone by
-// lbm_batch_destroy.
+// ties going to the taller tiles (fewer halo rows); a batch of one domain
+// leaves it at its own automatic height.  The choice is undone by
+// lbm_batch_destroy (lbm_batch_release can keep it for the next batch).
 static int batch_auto_rows(lbm_batch* b) {
-  if (b->doms.size() < 2) return LBM_OK;
   bool any = false;
   for (lbm_domain* d : b->doms) any = any || d->rows == 0;
   if (!any) return LBM_OK;
-  const long long simds = b->doms[0]->simds;
-  int pick = 8;
-  long long best = -1;
-  for (int r = 4; r <= 8; ++r) {
-    long long waves = 0;
-    for (lbm_domain* d : b->doms)
-      waves += (d->rows == 0 ? lbm_tile_count(d->P.nx, d->P.ny, r) : d->ntiles) + kFin;
-    const long long cost = (waves + simds - 1) / simds * (r + 4);
-    if (best < 0 || cost <= best) {
-      best = cost;
-      pick = r;
+  int pick = 0;  // a lone domain takes its own automatic height
+  if (b->doms.size() >= 2) {
+    const long long simds = b->doms[0]->simds;
+    long long best = -1;
+    for (int r = 4; r <= 8; ++r) {
+      long long waves = 0;
+      for (lbm_domain* d : b->doms)
+        waves += (d->rows == 0 ? lbm_tile_count(d->P.nx, d->P.ny, r) : d->ntiles) + kFin;
+      const long long cost = (waves + simds - 1) / simds * (r + 4);
+      if (best < 0 || cost <= best) {
+        best = cost;
+        pick = r;
+      }
     }
   }
+  bool changed = false;
   for (lbm_domain* d : b->doms) {
-    if (d->rows != 0) continue;
+    // a domain a previous batch left at this height (lbm_batch_release
+    // keeping the tiles) keeps its tiles
+    if (d->rows != 0 || d->batch_rows == pick) continue;
     d->batch_rows = pick;
     d->in_batch = false;
     int rc = lbm_set_tile_rows(d, 0);
@@ -263,8 +268,9 @@ static int batch_auto_rows(lbm_batch* b) {
     if (rc) return rc;
     d->host.parity = (int)((d->step - b->k) & 1);
     HIPCHECK(hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice));
+    changed = true;
   }
-  return build_groups(b);
+  return changed ? build_groups(b) : LBM_OK;
 }
 
 // Retile every domain (rows per tile) keeping the pending reductions.
@@ -443,7 +449,13 @@ extern "C" int lbm_batch_sync(lbm_batch* b) {
   return LBM_OK;
 }
 
-extern "C" int lbm_batch_destroy(lbm_batch* b) {
+// The domains leave the batch, which is freed.  Unless keep_tiles, each
+// domain gets its own rows setting back (lbm_batch_destroy); with
+// keep_tiles the domains stay tiled at the batch's heights, so that the next
+// batch built from them at the same height retiles none of them (the
+// serving loop rebuilds its batch whenever the running set changes; every
+// retile waits for a few small copies per domain).
+int lbm_batch_release(lbm_batch* b, bool keep_tiles) {
   if (!b) return LBM_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_batch_graph(b);
@@ -459,7 +471,7 @@ extern "C" int lbm_batch_destroy(lbm_batch* b) {
     d->host.parity = 0;
     (void)hipMemcpy(d->dev, &d->host, sizeof(DevDomain), hipMemcpyHostToDevice);
     const int own = i < b->saved_rows.size() ? b->saved_rows[i] : d->rows;
-    if (d->batch_rows || d->rows != own) {
+    if (!keep_tiles && (d->batch_rows || d->rows != own)) {
       // back to the domain's own rows (the batch height or the autotuner's
       // choice undone; pending sums carried over)
       d->batch_rows = 0;
@@ -470,3 +482,5 @@ extern "C" int lbm_batch_destroy(lbm_batch* b) {
   delete b;
   return rc;
 }
+
+extern "C" int lbm_batch_destroy(lbm_batch* b) { return lbm_batch_release(b, false); }

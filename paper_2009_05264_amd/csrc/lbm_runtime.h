@@ -58,3 +58,6 @@ int lbm_nonfinite_seen(lbm_domain* d, int* seen);
 // Replay graphs of a batch captured only when a call needs them (the serving
 // loop rebuilds its batch whenever the running set changes).
 void lbm_batch_lazy_graphs(lbm_batch* b);
+// lbm_batch_destroy, optionally leaving the domains at the batch's tile
+// heights (lbm_batch.cpp).
+int lbm_batch_release(lbm_batch* b, bool keep_tiles);

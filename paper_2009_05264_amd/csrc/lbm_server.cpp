@@ -94,9 +94,11 @@ extern "C" int lbm_admission_plan(const size_t* footprints, int n, size_t cap, s
   return LBM_OK;
 }
 
+// The requests' domains keep the batch's tile heights: most of them join the
+// next batch, whose automatic height is then usually the same.
 static int drop_batch(lbm_server* s) {
   if (s->batch) {
-    int rc = lbm_batch_destroy(s->batch);
+    int rc = lbm_batch_release(s->batch, true);
     s->batch = nullptr;
     if (rc) return rc;
   }

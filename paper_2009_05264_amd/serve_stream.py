@@ -15,9 +15,11 @@ which an arrival is only submitted once the quantum on the device is over).  Rep
 makespan), p50/p99 time to solution of the completed requests, the requests
 the server failed (fields turned non-finite; they are retired and freed
 while the others go on), and optionally checks sampled requests against the
-same solve run alone.
+same solve run alone, timing those solo runs (alone_MLUPS: the rate of the
+same requests one at a time, the GPU to themselves).
 
     python3 paper_2009_05264_amd/serve_stream.py --requests 256 --rate 4
+    python3 paper_2009_05264_amd/serve_stream.py --requests 256 --rate 1000   # saturated
 """
 from __future__ import annotations
 
@@ -121,6 +123,7 @@ def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0,
            "failed_nonfinite": sorted(failed), "completed": int(len(t))}
     if check:
         bad = []
+        solo_lups, solo_s = 0.0, 0.0
         for k, rho_mix in kept.items():
             _, cfg, storage, budget = reqs[k]
             d = L.Domain(params_of(L, W, cfg, storage), stream=stream)
@@ -128,12 +131,20 @@ def run_stream(n=64, rate=4.0, lo=5000, hi=50000, p16=0.5, seed=5, cap_gb=200.0,
             d.set_wall(L.SIDE_S, Ts, rws, heat)
             d.set_wall(L.SIDE_N, Tn, rwn)
             d.init(**cfg.init_args())
+            d.step(0)  # replay graphs captured outside the timing
+            d.sync()
+            t1 = time.perf_counter()
             d.step(budget)
+            d.sync()
+            solo_s += time.perf_counter() - t1
+            solo_lups += float(cfg.nx) * cfg.ny * budget
             if not np.array_equal(d.fields()["rho"], rho_mix):
                 bad.append(k)
             d.close()
         out["alone_vs_mix_checked"] = len(kept)
         out["alone_vs_mix_mismatch"] = bad
+        if solo_s > 0:
+            out["alone_MLUPS"] = round(solo_lups / solo_s / 1e6, 1)
     return out
 
 
