@@ -84,17 +84,14 @@ constexpr int kGraphLevels = 8;
 // whatever the host does meanwhile.
 constexpr int64_t kGraphMinSteps = 64;
 
-// Captures the graphs a call needs (all of them when eager), before any of
-// them is launched: a capture never lands between launches of a call.
-static int ensure_graphs(hipStream_t s, std::vector<GraphEntry>& g, int64_t pairs, int p, bool eager,
-                         int (*enqueue)(void*, int), void* ctx) {
+// Captures every replay graph not captured yet, before any of them is
+// launched: a capture never lands between launches of a call.
+static int ensure_graphs(hipStream_t s, std::vector<GraphEntry>& g, int (*enqueue)(void*, int), void* ctx) {
   if ((int)g.size() < 2 * kGraphLevels) g.resize(2 * kGraphLevels);
-  const int top = kGraphLevels - 1;
   for (int q = 0; q < 2; ++q)
     for (int k = 0; k < kGraphLevels; ++k) {
-      const bool needed = q == p && (k == top ? (pairs >> top) > 0 : ((pairs >> k) & 1) != 0);
       GraphEntry& e = g[q * kGraphLevels + k];
-      if (e.exec || !(eager || needed)) continue;
+      if (e.exec) continue;
       int rc = capture_pairs(s, &e, 1 << k, q, enqueue, ctx);
       if (rc) return rc;
     }
@@ -104,12 +101,12 @@ static int ensure_graphs(hipStream_t s, std::vector<GraphEntry>& g, int64_t pair
 // Replays the even part of n steps, the first of launch phase p; *done
 // counts the steps enqueued (the at most one step left over is the
 // caller's).
-static int replay_steps(hipStream_t s, std::vector<GraphEntry>& g, int64_t n, int p, bool eager,
+static int replay_steps(hipStream_t s, std::vector<GraphEntry>& g, int64_t n, int p,
                         int (*enqueue)(void*, int), void* ctx, int64_t* done) {
   *done = 0;
   const int64_t pairs = n / 2;
   if (pairs == 0) return LBM_OK;
-  int rc = ensure_graphs(s, g, pairs, p, eager, enqueue, ctx);
+  int rc = ensure_graphs(s, g, enqueue, ctx);
   if (rc) return rc;
   const int top = kGraphLevels - 1;
   GraphEntry* set = &g[p * kGraphLevels];
@@ -137,14 +134,14 @@ static int enqueue_domain_phase(void* ctx, int phase) {
 
 int lbm_run_steps(lbm_domain* d, int64_t n) {
   if (d->in_batch) return lbm_fail(LBM_E_STATE, "domain is part of a batch; step the batch");
-  if (n == 0) return ensure_graphs(d->stream, d->graphs, 0, 0, true, enqueue_domain_phase, d);
+  if (n == 0) return ensure_graphs(d->stream, d->graphs, enqueue_domain_phase, d);
   if (n < kGraphMinSteps) return lbm_enqueue_steps(d, n);
   const int64_t head = head_launches(n);
   int rc = lbm_enqueue_steps(d, head);
   if (rc) return rc;
   n -= head;
   int64_t done = 0;
-  rc = replay_steps(d->stream, d->graphs, n, (int)(d->step & 1), true, enqueue_domain_phase, d, &done);
+  rc = replay_steps(d->stream, d->graphs, n, (int)(d->step & 1), enqueue_domain_phase, d, &done);
   d->step += done;
   return rc;
 }
@@ -166,7 +163,7 @@ struct lbm_batch {
   std::vector<Group> groups;
   std::vector<GraphEntry> graphs;  // [p * kGraphLevels + k]: 2^k launch pairs from phase p
   GraphEntry probe;                // the autotuner's timing graph (one launch pair)
-  bool eager = true;               // capture every replay graph on first use
+  bool plain = false;              // every step a single launch (lbm_batch_plain_launches)
   int64_t k = 0;  // steps done by the batch
   int rows = kDefaultTileRows;
   std::vector<int> saved_rows;  // each domain's own rows setting, restored by lbm_batch_destroy
@@ -423,21 +420,21 @@ extern "C" int lbm_batch_create(lbm_domain* const* doms, int n, const char* tune
   return LBM_OK;
 }
 
-void lbm_batch_lazy_graphs(lbm_batch* b) {
-  if (b) b->eager = false;
+void lbm_batch_plain_launches(lbm_batch* b) {
+  if (b) b->plain = true;
 }
 
 extern "C" int lbm_batch_step(lbm_batch* b, int64_t n) {
   if (!b) return lbm_fail(LBM_E_INVALID, "batch is NULL");
   if (n < 0) return lbm_fail(LBM_E_INVALID, "nsteps must be >= 0");
-  if (n == 0) return ensure_graphs(b->stream, b->graphs, 0, 0, true, enqueue_batch_phase, b);
-  if (n < kGraphMinSteps) return batch_steps_plain(b, n);
+  if (n == 0) return b->plain ? LBM_OK : ensure_graphs(b->stream, b->graphs, enqueue_batch_phase, b);
+  if (n < kGraphMinSteps || b->plain) return batch_steps_plain(b, n);
   const int64_t head = head_launches(n);
   int rc = batch_steps_plain(b, head);
   if (rc) return rc;
   n -= head;
   int64_t done = 0;
-  rc = replay_steps(b->stream, b->graphs, n, (int)(b->k & 1), b->eager, enqueue_batch_phase, b, &done);
+  rc = replay_steps(b->stream, b->graphs, n, (int)(b->k & 1), enqueue_batch_phase, b, &done);
   b->k += done;
   for (lbm_domain* d : b->doms) d->step += done;
   return rc;

@@ -55,9 +55,9 @@ int lbm_enqueue_steps(lbm_domain* d, int64_t n);
 int lbm_run_steps(lbm_domain* d, int64_t n);
 void lbm_drop_graphs(lbm_domain* d);
 int lbm_nonfinite_seen(lbm_domain* d, int* seen);
-// Replay graphs of a batch captured only when a call needs them (the serving
-// loop rebuilds its batch whenever the running set changes).
-void lbm_batch_lazy_graphs(lbm_batch* b);
+// Every step of the batch a single launch, with no replay graphs to capture
+// (the serving loop rebuilds its batch whenever the running set changes).
+void lbm_batch_plain_launches(lbm_batch* b);
 // lbm_batch_destroy, optionally leaving the domains at the batch's tile
 // heights (lbm_batch.cpp).
 int lbm_batch_release(lbm_batch* b, bool keep_tiles);
