@@ -275,8 +275,9 @@ def test_repeatable_and_graph_equals_plain(L):
 
 def test_long_graphs_equal_plain(L):
     """Calls long enough for the 256-launch replay graph and its repeats
-    (700 steps from an odd and from an even step), and a batch call of 600
-    steps, equal the same steps in calls of 50 single launches, bitwise."""
+    (700 steps from an odd and from an even step), and batch calls of 600
+    steps (from an even and from an odd batch step), equal the same steps in
+    calls of 50 single launches, bitwise."""
     cfg = W.c1()
     out = []
     for split in ((1, 700, 300), (2, 700, 299), (1,) + (50,) * 20):
@@ -289,9 +290,9 @@ def test_long_graphs_equal_plain(L):
     for k in out[0]:
         for o in out[1:]:
             assert np.array_equal(out[0][k], o[k]), k
-    # batch: 600 steps in one call against 12 calls of 50
+    # batch: 601 steps as 600 + 1, 1 + 600 and 1 + 12 calls of 50
     res = []
-    for calls in ((600,), (50,) * 12):
+    for calls in ((600, 1), (1, 600), (1,) + (50,) * 12):
         doms = []
         for c in (W.c1(), W.Channel(nx=130, ny=30, heater_len=10, seed=5)):
             d = make_gpu(L, c)
@@ -303,9 +304,10 @@ def test_long_graphs_equal_plain(L):
         bt.sync()
         bt.close()
         res.append([d.fields() for d in doms])
-    for fa, fb in zip(res[0], res[1]):
-        for k in fa:
-            assert np.array_equal(fa[k], fb[k]), k
+    for other in res[1:]:
+        for fa, fb in zip(res[0], other):
+            for k in fa:
+                assert np.array_equal(fa[k], fb[k]), k
 
 
 def test_checkpoint_resume_bitwise(L, tmp_path):
